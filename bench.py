@@ -1,0 +1,144 @@
+"""Benchmark of the fused LSRK4 stage kernel: DOF-updates/s on one MI355X.
+
+A "step" is one full five-stage LSRK4 step of the whole hot path (volume
+differentiation, face gather + upwind flux, LIFT, RK update, fused in one
+kernel per stage) over the 2D TM PEC cavity: 256x256 grid -> 131072
+randomly permuted, jittered triangles, order N=5 (Np=21), mode (2,3), CFL
+time step.  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--config c2|c3|c1] [--no-cpu]
+
+Prints one JSON line (metric, value, roofline, cpu_baseline, accuracy).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s (FP32 vs split-BF16 at stated L2 err); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    # name: (grid s, mesh seed, permute, order N, mode, description)
+    "c1": (8, 1, False, 3, (1, 1), "2D TM PEC cavity, 8x8 grid -> 128 triangles, N=3, mode (1,1)"),
+    "c2": (256, 2, True, 5, (2, 3), "2D TM PEC cavity, 256x256 grid -> 131072 randomly permuted triangles "
+                                    "(interior vertices jittered +-0.1h), N=5 (Np=21), mode (2,3), "
+                                    "5-stage LSRK4 at the CFL step"),
+    "c3": (512, 3, False, 7, (2, 3), "2D TM PEC cavity, 512x512 grid -> 524288 triangles, N=7 (Np=36), "
+                                     "mode (2,3), 5-stage LSRK4 at the CFL step"),
+}
+
+
+def cpu_baseline(mesh, N, mode, stages: int = 10):
+    """The FP64 oracle as it stands, on this host's cores, over a bounded
+    sample of the same workload: `stages` RK stages on the full mesh."""
+    import numpy as np
+
+    import oracle
+    from oracle.maxwell import LSRK4_A, LSRK4_B
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    cores = min(threads, len(os.sched_getaffinity(0)))
+    d = oracle.Discretization2D(mesh.vx, mesh.vy, mesh.elem_verts, N)
+    op = oracle.Maxwell2D(d)
+    dt = oracle.cfl_dt(d, N)
+    q = oracle.cavity_mode_2d(d.x, d.y, 0.0, *mode)
+    res = np.zeros_like(q)
+    # one untimed stage, then the timed sample
+    res = LSRK4_A[0] * res + dt * op.rhs(q)
+    q = q + LSRK4_B[0] * res
+    t0 = time.perf_counter()
+    for i in range(stages):
+        s = (i + 1) % 5
+        res = LSRK4_A[s] * res + dt * op.rhs(q)
+        q = q + LSRK4_B[s] * res
+    el = time.perf_counter() - t0
+    dofs = 3 * d.K * d.Np
+    return {"value": dofs * stages / 5.0 / el, "unit": "DOF-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{stages} LSRK4 stages (= {stages / 5:g} steps) of the FP64 NumPy oracle on the full "
+                      f"{d.K}-element mesh, {el:.1f} s wall, BLAS threads {threads}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU halo exchange is design-only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1304_5546_amd import dgw, inputs
+
+    s_grid, seed, permute, N, mode, desc = CONFIGS[args.config]
+    mesh = inputs.tri_grid(s_grid, seed=seed, permute=permute)
+    stream = torch.cuda.Stream()
+    solver = dgw.Solver(mesh, N, stream=stream)
+    dt = solver.cfl_dt()
+    solver.set_cavity_mode(*mode)
+    bytes_per_launch, flops_per_launch = solver.stage_cost()
+
+    solver.launch_steps(args.warmup, dt, stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    solver.launch_steps(args.steps, dt, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    t_reached = (args.warmup + args.steps) * dt
+    err = solver.cavity_error(mode[0], mode[1], 0, t_reached)
+
+    dofs = solver.n_fields * solver.K * solver.Np
+    value = dofs * args.steps / (ms * 1e-3)
+    launch_s = ms * 1e-3 / (5 * args.steps)
+    achieved = bytes_per_launch / launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "K": solver.K, "N": N, "Np": solver.Np, "dofs": dofs, "dt": dt,
+                   "t_reached": t_reached, "precision": "fp32"},
+        "accuracy": {"rel_l2_vs_closed_form": err, "t": t_reached},
+        "gflops_paper_model": flops_per_launch / launch_s / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"stage2d_kernel<{N}, false>", "avg_launch_us": launch_s * 1e6,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    solver.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, N, mode)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * dgw.h -- C ABI of libdgw.so, the MI355X (gfx950) nodal discontinuous
+ * Galerkin Maxwell solver hot path.
+ *
+ * What it computes (Kloeckner, Warburton, Hesthaven, "Solving Wave Equations
+ * on Unstructured Geometries"):
+ *   - the initial boundary value problem of the section "A Precise
+ *     Mathematical Problem Statement": 2D transverse-magnetic Maxwell
+ *     (eq. tm-maxwells, with +dEz/dx in the Hy equation) or 3D Maxwell
+ *     (section "Adding Generality", three dimensions) on a polyhedral domain
+ *     meshed by straight-sided, face-conforming simplices, with a perfectly
+ *     electrically conducting (PEC) wall, no source, initial fields at t = 0;
+ *   - the semi-discrete DG operator of eq. dg-strong-explicit: element-local
+ *     differentiation by the reference matrices Dr/Ds(/Dt) with per-element
+ *     geometric factors (eq. dg-diff-local-to-global), the face gather with
+ *     the upwind flux of eq. max2d-numflux (factor 1/2, jumps
+ *     [q] = q^- - q^+), and the LIFT = M^{-1} M^{dI} apply of eq. dg-lift;
+ *   - an explicit Runge-Kutta method in time (section "Implementation
+ *     Aspects"): five-stage, fourth-order, 2N-storage LSRK (Carpenter and
+ *     Kennedy 1994), fused with the right-hand side into one kernel per stage.
+ *
+ * Conventions
+ *   - Every call returns DGW_OK (0) or a negative DGW_E* code; the text of
+ *     the last error on the calling thread is available from dgw_last_error().
+ *     No exception crosses the ABI.
+ *   - Pointers passed in are caller-owned and read (or written) only during
+ *     the call.  Handles are library-owned until the matching destroy call.
+ *   - A solver handle must not be used from two threads at once; the server
+ *     calls are thread-safe.
+ *   - Element order in every array is the caller's order given at creation,
+ *     whatever the internal renumbering.  Node order inside an element is the
+ *     lattice order of the equispaced set the warp & blend node map starts
+ *     from: 2D for j in 0..N, for i in 0..N-j (node (i, j)); 3D for k in 0..N,
+ *     for j in 0..N-k, for i in 0..N-j-k.  Reference simplex vertices:
+ *     2D (-1,-1), (1,-1), (-1,1); 3D (-1,-1,-1), (1,-1,-1), (-1,1,-1),
+ *     (-1,-1,1); element vertex v_i of elem_verts maps to reference vertex i.
+ *   - Field arrays are [n_fields][K][Np], FP64 on the host.  n_fields = 3 in
+ *     2D (Hx, Hy, Ez) and 6 in 3D (Hx, Hy, Hz, Ex, Ey, Ez).
+ */
+#ifndef DGW_H
+#define DGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define DGW_OK           0
+#define DGW_EINVAL      -1   /* bad argument (NULL, size, enum)              */
+#define DGW_EMESH       -2   /* J <= 0, non-conforming face, bad vertex id   */
+#define DGW_EORDER      -3   /* order outside 1..8 (2D) / 1..6 (3D)          */
+#define DGW_ENOMEM      -4   /* host or device allocation failed             */
+#define DGW_ETOOBIG     -5   /* footprint exceeds a size limit or budget     */
+#define DGW_EDEVICE     -6   /* HIP runtime error (text in dgw_last_error)   */
+#define DGW_ENONFINITE  -7   /* a field became NaN/Inf                       */
+#define DGW_ECANCELLED  -8   /* request cancelled                            */
+#define DGW_ENOTFOUND   -9   /* unknown ticket                               */
+#define DGW_ENODEVICE  -10   /* call needs a device, handle is host-only     */
+
+/* Static text for a code. */
+const char *dgw_strerror(int code);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *dgw_last_error(void);
+
+/* ------------------------------------------------------------------ inputs */
+/* Mesh of straight-sided simplices (section "Construction of the Method":
+ * straight-sided, face-conforming triangles; tetrahedra in 3D).
+ * vx, vy (and vz in 3D): n_verts coordinates.  elem_verts: n_elems x (dim+1)
+ * vertex ids, each element positively oriented (J > 0, counter-clockwise in
+ * 2D); a face is shared by at most two elements and faces shared by none are
+ * the PEC wall.  eps, mu: per-element relative permittivity/permeability
+ * (NULL means 1); the 3D path supports eps = mu = 1 only. */
+typedef struct {
+    int32_t dim;                 /* 2 or 3 */
+    int64_t n_verts;
+    const double *vx, *vy, *vz;  /* vz NULL in 2D */
+    int64_t n_elems;
+    const int32_t *elem_verts;
+    const double *eps, *mu;
+} dgw_mesh;
+
+typedef enum {
+    DGW_FP32 = 0,        /* all contractions in FP32                              */
+    DGW_SPLIT_BF16 = 1,  /* Dr/Ds/LIFT as BF16 hi+lo split products, FP32 accum.  */
+    DGW_SPLIT_FP16 = 2   /* same with FP16 hi+lo split products                   */
+} dgw_precision;
+
+typedef struct {
+    double alpha;        /* flux parameter: 1 upwind (default), 0 central          */
+    double cfl;          /* multiplier on the CFL step rule (default 1)           */
+    int32_t prec;        /* dgw_precision                                         */
+    int32_t renumber;    /* 1 (default): space-filling-curve element order on GPU */
+    int32_t device;      /* HIP device ordinal; -1 = host-only handle (setup only)*/
+    int32_t reserved;
+    void *hip_stream;    /* hipStream_t to launch on; NULL = library's own stream */
+} dgw_opts;
+
+/* Fill *o with the defaults (alpha 1, cfl 1, FP32, renumber 1, device 0). */
+int dgw_opts_default(dgw_opts *o);
+
+/* ------------------------------------------------------------------ reference element (host only) */
+/* Nodal reference element of the given dim and order (section
+ * "Implementation Aspects": Lagrange basis on warp & blend nodes, operators
+ * from orthonormal simplex polynomials).  Any output pointer may be NULL.
+ *   r, s, t : Np node coordinates (t only in 3D)
+ *   Dr, Ds, Dt : Np x Np row-major differentiation matrices
+ *   M : Np x Np mass matrix;  LIFT : Np x (Nfaces*Nfp) row-major, columns
+ *   ordered face by face, each face's nodes in the order of dgw_face_nodes.
+ *   face_nodes : Nfaces x Nfp volume-node indices of each face. */
+int dgw_reference_element(int32_t dim, int32_t order, int32_t *Np, int32_t *Nfp,
+                          double *r, double *s, double *t, double *Dr, double *Ds,
+                          double *Dt, double *M, double *LIFT, int32_t *face_nodes);
+
+/* ------------------------------------------------------------------ solver */
+typedef struct dgw_solver dgw_solver;
+
+typedef struct {
+    int64_t steps;            /* steps taken by the last advance              */
+    double dt;                /* step used                                    */
+    double t;                 /* simulated time reached since set_fields      */
+    double setup_s;           /* host setup + upload of dgw_create            */
+    double solve_ms;          /* device time of the last advance (HIP events) */
+    double dof_updates_per_s; /* n_fields*K*Np*steps / solve time             */
+} dgw_info;
+
+/* Set up the discretisation of order `order` on `mesh` (host FP64), upload
+ * operators and geometry, allocate the fields (zero).  Errors: EINVAL,
+ * EMESH, EORDER, ENOMEM, EDEVICE. */
+int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts, dgw_solver **out);
+void dgw_destroy(dgw_solver *s);
+
+int dgw_sizes(const dgw_solver *s, int64_t *K, int32_t *Np, int32_t *n_fields);
+/* Physical node coordinates, [K][Np] each, caller order (z NULL in 2D). */
+int dgw_node_coords(const dgw_solver *s, double *x, double *y, double *z);
+/* Time step of the CFL rule: cfl * (1/2) * min LGL spacing(N) *
+ * min_k inradius_k sqrt(eps_k mu_k). */
+int dgw_cfl_dt(const dgw_solver *s, double *dt);
+
+/* Fields in/out, FP64 host arrays [n_fields][K][Np] (converted to the device
+ * precision).  set_fields zeroes the RK residual and the time. */
+int dgw_set_fields(dgw_solver *s, const double *q);
+int dgw_get_fields(dgw_solver *s, double *q);
+/* Initialise on the device, in FP64, the closed-form PEC cavity mode at t=0:
+ * 2D Ez = sin(m pi x) sin(n pi y), H = 0 (mode = {m, n, -});
+ * 3D E = (n cos(m pi x) sin(n pi y) sin(l pi z), -m sin cos sin, 0), H = 0. */
+int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]);
+
+/* Take `nsteps` LSRK4 steps of size dt (dt <= 0: the CFL step).  Launches
+ * five fused stage kernels per step on the solver's stream, no host sync
+ * inside the loop; returns after the stream has drained. */
+int dgw_advance_steps(dgw_solver *s, int64_t nsteps, double dt);
+/* Advance to t_final: with dt <= 0 the step is the CFL step shortened to
+ * t_final / ceil(t_final / dt_cfl). */
+int dgw_advance(dgw_solver *s, double t_final, double dt, int64_t *steps_taken);
+
+/* One evaluation of the semi-discrete right-hand side L(q) by the same fused
+ * stage kernel (RK coefficients a = 0, dt = 1, b = 0): q and rhs are FP64 host
+ * arrays [n_fields][K][Np].  Leaves the solver's fields and residual
+ * overwritten with q and L(q). */
+int dgw_rhs(dgw_solver *s, const double *q, double *rhs);
+
+/* FP64 device reduction of the discrete energy
+ * 0.5 * sum_k J_k sum_f w_f q_f^T M q_f (w = mu for H, eps for E). */
+int dgw_energy(dgw_solver *s, double *energy);
+/* FP64 device reduction of the relative L2 error (mass-matrix norm, unit field
+ * weights) of the current fields against the closed-form cavity mode at time
+ * t (2D: uniform eps, mu of element 0; 3D: eps = mu = 1). */
+int dgw_cavity_error(dgw_solver *s, const int32_t mode[3], double t, double *rel_l2);
+
+int dgw_last_info(const dgw_solver *s, dgw_info *info);
+
+/* Device-pointer plumbing for callers holding FP32 device buffers (e.g. torch
+ * tensors): q_dev is [n_fields][K][Np] FP32 in caller order on the solver's
+ * device, stream a hipStream_t (NULL = solver stream).  Asynchronous on that
+ * stream. */
+int dgw_set_fields_dev(dgw_solver *s, const float *q_dev, void *stream);
+int dgw_get_fields_dev(dgw_solver *s, float *q_dev, void *stream);
+/* Launch `nsteps` steps on `stream` without waiting (for timing by the
+ * caller); dt must be > 0. */
+int dgw_launch_steps(dgw_solver *s, int64_t nsteps, double dt, void *stream);
+/* Kernel name and per-launch algorithmic HBM bytes and flops of one fused
+ * stage (the units behind the roofline figures). */
+int dgw_stage_cost(const dgw_solver *s, double *bytes, double *flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGW_H */

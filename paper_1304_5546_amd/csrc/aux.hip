@@ -1,0 +1,186 @@
+// FP64 reductions (energy, error against the closed-form cavity mode), the
+// on-device FP64 cavity-mode initialisation and the layout permutations
+// between the caller's element-major and the internal node-major layout.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device.hpp"
+
+namespace dgw {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+
+// deterministic block reduction of one double per thread
+__device__ double block_sum(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kRedThreads / 64; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// one thread per element: sum_f w_f q_f^T M q_f J
+__global__ void __launch_bounds__(kRedThreads) energy_kernel(ReduceArgs a) {
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    for (int e = blockIdx.x * kRedThreads + threadIdx.x; e < a.K; e += gridDim.x * kRedThreads) {
+        double ek = 0.0;
+        for (int f = 0; f < a.nf; ++f) {
+            double qf = 0.0;
+            for (int i = 0; i < a.Np; ++i) {
+                const double qi = a.q[(size_t)(f * a.Np + i) * a.Kp + e];
+                double mq = 0.0;
+                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * (double)a.q[(size_t)(f * a.Np + j) * a.Kp + e];
+                qf += qi * mq;
+            }
+            ek += (a.w ? a.w[(size_t)f * a.Kp + e] : 1.0) * qf;
+        }
+        acc += a.J[e] * ek;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+}
+
+__device__ void cavity_exact(const CavityArgs &a, double x, double y, double z, double *out) {
+    const double pi = M_PI;
+    if (a.dim == 2) {
+        const double w = pi * sqrt(double(a.m * a.m + a.n * a.n)) / sqrt(a.eps * a.mu);
+        const double sx = sin(a.m * pi * x), cx = cos(a.m * pi * x);
+        const double sy = sin(a.n * pi * y), cy = cos(a.n * pi * y);
+        const double ct = cos(w * a.t), st = sin(w * a.t);
+        out[0] = -(a.n * pi / (a.mu * w)) * sx * cy * st;
+        out[1] = (a.m * pi / (a.mu * w)) * cx * sy * st;
+        out[2] = sx * sy * ct;
+    } else {
+        // E = (Ax cx sy sz, Ay sx cy sz, Az sx sy cz) cos(wt), A = (n, -m, 0),
+        // H = -(1/w) curl(E_spatial) sin(wt), w = pi sqrt(m^2+n^2+l^2)
+        const double km = a.m * pi, kn = a.n * pi, kl = a.l * pi;
+        const double w = sqrt(km * km + kn * kn + kl * kl);
+        const double Ax = a.n, Ay = -a.m, Az = 0.0;
+        const double sx = sin(km * x), cx = cos(km * x), sy = sin(kn * y), cy = cos(kn * y);
+        const double sz = sin(kl * z), cz = cos(kl * z);
+        const double ct = cos(w * a.t), st = sin(w * a.t);
+        // curl of the spatial E
+        const double cxE = (Az * kn - Ay * kl) * sx * cy * cz;
+        const double cyE = (Ax * kl - Az * km) * cx * sy * cz;
+        const double czE = (Ay * km - Ax * kn) * cx * cy * sz;
+        out[0] = -cxE * st / w;
+        out[1] = -cyE * st / w;
+        out[2] = -czE * st / w;
+        out[3] = Ax * cx * sy * sz * ct;
+        out[4] = Ay * sx * cy * sz * ct;
+        out[5] = Az * sx * sy * cz * ct;
+    }
+}
+
+__global__ void cavity_init_kernel(CavityArgs a) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = a.dim == 2 ? 3 : 6;
+    if (e >= a.Kp) return;
+    for (int i = 0; i < a.Np; ++i) {
+        double out[6] = {0, 0, 0, 0, 0, 0};
+        if (e < a.K) {
+            const size_t p = (size_t)i * a.Kp + e;
+            cavity_exact(a, a.x[p], a.y[p], a.dim == 3 ? a.z[p] : 0.0, out);
+        }
+        for (int f = 0; f < nf; ++f) a.q[(size_t)(f * a.Np + i) * a.Kp + e] = (float)out[f];
+    }
+}
+
+// one thread per element; accumulates ||q - q_exact||^2_M and ||q_exact||^2_M
+// (the closed form is re-evaluated inside the M product instead of being
+// stored, keeping the kernel free of large per-lane arrays)
+__global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a) {
+    __shared__ double sh[kRedThreads / 64];
+    const int nf = a.dim == 2 ? 3 : 6;
+    double num = 0.0, den = 0.0;
+    for (int e = blockIdx.x * kRedThreads + threadIdx.x; e < a.K; e += gridDim.x * kRedThreads) {
+        double nk = 0.0, dk = 0.0;
+        for (int i = 0; i < a.Np; ++i) {
+            const size_t pi = (size_t)i * a.Kp + e;
+            double exi[6], di[6], md[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
+            cavity_exact(a, a.x[pi], a.y[pi], a.dim == 3 ? a.z[pi] : 0.0, exi);
+            for (int f = 0; f < nf; ++f) di[f] = (double)a.q[(size_t)(f * a.Np + i) * a.Kp + e] - exi[f];
+            for (int j = 0; j < a.Np; ++j) {
+                const size_t pj = (size_t)j * a.Kp + e;
+                double exj[6];
+                cavity_exact(a, a.x[pj], a.y[pj], a.dim == 3 ? a.z[pj] : 0.0, exj);
+                const double Mij = a.Mref[i * a.Np + j];
+                for (int f = 0; f < nf; ++f) {
+                    md[f] += Mij * ((double)a.q[(size_t)(f * a.Np + j) * a.Kp + e] - exj[f]);
+                    mx[f] += Mij * exj[f];
+                }
+            }
+            for (int f = 0; f < nf; ++f) {
+                nk += di[f] * md[f];
+                dk += exi[f] * mx[f];
+            }
+        }
+        num += a.J[e] * nk;
+        den += a.J[e] * dk;
+    }
+    const double s1 = block_sum(num, sh);
+    const double s2 = block_sum(den, sh);
+    if (threadIdx.x == 0) {
+        a.partial[2 * blockIdx.x] = s1;
+        a.partial[2 * blockIdx.x + 1] = s2;
+    }
+}
+
+__global__ void to_internal_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf) {
+    const size_t total = (size_t)nf * Np * Kp;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int e = int(t % Kp);
+        const size_t fn = t / Kp;
+        const int n = int(fn % Np), f = int(fn / Np);
+        dst[t] = e < K ? src[((size_t)f * K + perm[e]) * Np + n] : 0.0f;
+    }
+}
+
+__global__ void to_caller_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf) {
+    const size_t total = (size_t)nf * Np * K;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int e = int(t % K);
+        const size_t fn = t / K;
+        const int n = int(fn % Np), f = int(fn / Np);
+        dst[((size_t)f * K + perm[e]) * Np + n] = src[(size_t)(f * Np + n) * Kp + e];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_energy(const ReduceArgs &a, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(energy_kernel, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cavity_init(const CavityArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(cavity_init_kernel, dim3((a.Kp + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cavity_error(const CavityArgs &a, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(cavity_error_kernel, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_internal(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(to_internal_kernel, dim3(2048), dim3(256), 0, s, src, dst, perm, K, Kp, Np, nf);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_caller(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(to_caller_kernel, dim3(2048), dim3(256), 0, s, src, dst, perm, K, Kp, Np, nf);
+    return hipGetLastError();
+}
+
+}  // namespace dgw

@@ -1,0 +1,81 @@
+// Device-side data layout and launch wrappers of the fused LSRK stage.
+//
+// HBM layout (internal element order e = 0..Kp-1, Kp = K rounded up to the
+// 64-element tile; padding elements carry zero fields and geometry):
+//   q, res  : [n_fields][Np][Kp] FP32, node-major so that one wave's 64 lanes
+//             (64 consecutive elements of a tile) read one node of one field
+//             as 256 contiguous bytes
+//   geo     : [G][Kp] FP32 per-element factors: 2D r_x, r_y, s_x, s_y
+//             (+ 1/eps, 1/mu with materials); 3D the nine entries of A_k^{-1}
+//   fgeo    : [Nfaces][FG][Kp] FP32 per-face data: 2D n_x, n_y, Fscale, or
+//             n_x, n_y and four flux coefficients with materials; 3D n_x,
+//             n_y, n_z, Fscale
+//   nbr     : [Nfaces][Kp] int32 face record: -1 on the PEC wall, else
+//             (e' << 5) | (f' << 3) | orientation
+//   ops     : FP32 Dr, Ds (, Dt) [Np][Np] and LIFT [Np][Nfaces*Nfp], row-major
+//   itab    : int32 own face nodes [Nfaces*Nfp], then the partner node table
+//             [Nfaces][n_orient][Nfp] (volume node of the partner's face node)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgw {
+
+constexpr int kTile = 64;  // elements per work-group tile (one per lane)
+
+struct StageArgs {
+    const float *qin;
+    float *qout;
+    float *res;
+    const float *geo;
+    const float *fgeo;
+    const int *nbr;
+    const float *ops;
+    const int *itab;
+    int Kp;
+    int ntiles;
+    float a, b, dt, alpha;
+};
+
+// Launch one fused stage: res <- a res + dt L(qin); qout <- qin + b res.
+hipError_t launch_stage(int dim, int N, bool material, const StageArgs &args, hipStream_t stream);
+const char *stage_kernel_name(int dim, int N, bool material);
+
+// FP64 reductions: per-block partial sums of
+//   energy: J_k sum_f w_f q_f^T M q_f     (w from wvec: [n_fields][Kp] FP64 or NULL = 1)
+// into partial[nblocks].
+struct ReduceArgs {
+    const float *q;
+    const double *J;      // [Kp]
+    const double *Mref;   // [Np][Np]
+    const double *w;      // [n_fields][Kp] or nullptr
+    int Kp, K, Np, nf;
+    double *partial;
+};
+hipError_t launch_energy(const ReduceArgs &a, int nblocks, hipStream_t stream);
+
+// Relative L2 vs the closed-form cavity mode at time t: partial[2*b] is the
+// error mass norm squared, partial[2*b+1] the reference's.
+struct CavityArgs {
+    float *q;             // fields (written by init, read by error)
+    const double *x, *y, *z;   // node coordinates [Np][Kp]
+    const double *J;
+    const double *Mref;
+    int Kp, K, Np, dim;
+    int m, n, l;
+    double eps, mu, t;
+    double *partial;
+};
+hipError_t launch_cavity_init(const CavityArgs &a, hipStream_t stream);
+hipError_t launch_cavity_error(const CavityArgs &a, int nblocks, hipStream_t stream);
+
+// Layout permutation between the caller's [nf][K][Np] FP32 and the internal
+// node-major [nf][Np][Kp]; perm[e] = caller element at internal e (e < K).
+hipError_t launch_to_internal(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+                              hipStream_t stream);
+hipError_t launch_to_caller(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+                            hipStream_t stream);
+
+}  // namespace dgw

@@ -1,0 +1,670 @@
+// C ABI of libdgw.so: solver creation (host FP64 set-up, upload), field
+// transfer, the LSRK4 step loop of fused stage kernels, FP64 reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dgw.h"
+#include "device.hpp"
+#include "host.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+constexpr int kRedBlocks = 512;
+
+}  // namespace
+
+#define DGW_HIP(call)                                                                                     \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess) return fail(DGW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct dgw_solver {
+    dgw::RefElement ref;
+    dgw::Geometry g;
+    int dim = 2, N = 1, Np = 0, Nfp = 0, Nfaces = 0, nf = 0;
+    int64_t K = 0, Kp = 0;
+    int G = 0, FG = 0;
+    bool material = false;
+    dgw_opts opts{};
+    std::vector<int> perm;   // internal e -> caller k
+    std::vector<int> iperm;  // caller k -> internal e
+    double dt_cfl = 0.0;
+    bool on_device = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    float *q[2] = {nullptr, nullptr};
+    float *res = nullptr;
+    int cur = 0;
+    float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr;
+    int *nbr_d = nullptr, *itab_d = nullptr, *perm_d = nullptr;
+    double *J_d = nullptr, *M_d = nullptr, *w_d = nullptr, *x_d = nullptr, *y_d = nullptr, *z_d = nullptr;
+    double *partial_d = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    dgw_info info{};
+    double t = 0.0;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(T **p, size_t n) {
+    if (hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return fail(DGW_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    return DGW_OK;
+}
+
+template <typename T>
+int upload(T *dst, const std::vector<T> &src) {
+    DGW_HIP(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return DGW_OK;
+}
+
+void free_device(dgw_solver *s) {
+    if (!s->on_device) return;
+    hipSetDevice(s->opts.device);
+    void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->nbr_d, s->itab_d, s->perm_d,
+                    s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    if (s->ev0) hipEventDestroy(s->ev0);
+    if (s->ev1) hipEventDestroy(s->ev1);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    s->on_device = false;
+}
+
+int setup_device(dgw_solver *s) {
+    const int dim = s->dim, Np = s->Np, Nfp = s->Nfp, Nf = s->Nfaces, nf = s->nf;
+    const int64_t K = s->K, Kp = s->Kp;
+    const auto &g = s->g;
+    const auto &R = s->ref;
+    DGW_HIP(hipSetDevice(s->opts.device));
+    s->on_device = true;
+    if (s->opts.hip_stream) {
+        s->stream = (hipStream_t)s->opts.hip_stream;
+    } else {
+        DGW_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        s->own_stream = true;
+    }
+    DGW_HIP(hipEventCreate(&s->ev0));
+    DGW_HIP(hipEventCreate(&s->ev1));
+    const size_t nstate = (size_t)nf * Np * Kp;
+    int rc;
+    if ((rc = dalloc(&s->q[0], nstate)) || (rc = dalloc(&s->q[1], nstate)) || (rc = dalloc(&s->res, nstate)))
+        return rc;
+    DGW_HIP(hipMemset(s->q[0], 0, nstate * sizeof(float)));
+    DGW_HIP(hipMemset(s->q[1], 0, nstate * sizeof(float)));
+    DGW_HIP(hipMemset(s->res, 0, nstate * sizeof(float)));
+
+    // per-element factors
+    std::vector<float> geo((size_t)s->G * Kp, 0.0f);
+    std::vector<float> fgeo((size_t)Nf * s->FG * Kp, 0.0f);
+    std::vector<int> nbr((size_t)Nf * Kp, -1);
+    std::vector<double> J(Kp, 0.0), w(s->material ? (size_t)nf * Kp : 0, 0.0);
+    std::vector<double> X((size_t)Np * Kp, 0.0), Y((size_t)Np * Kp, 0.0), Z(dim == 3 ? (size_t)Np * Kp : 0, 0.0);
+    const double alpha = s->opts.alpha;
+    for (int64_t e = 0; e < K; ++e) {
+        const int64_t k = s->perm[e];
+        const double *D = &g.drst[(size_t)k * dim * dim];
+        for (int c = 0; c < dim * dim; ++c) geo[(size_t)c * Kp + e] = (float)D[c];
+        if (dim == 2 && s->material) {
+            geo[(size_t)4 * Kp + e] = (float)(1.0 / g.eps[k]);
+            geo[(size_t)5 * Kp + e] = (float)(1.0 / g.mu[k]);
+        }
+        J[e] = g.J[k];
+        if (s->material) {
+            // magnetic fields (Hx, Hy[, Hz]) weigh with mu, electric ones with eps
+            const int n_h = dim == 2 ? 2 : 3;
+            for (int f = 0; f < nf; ++f) w[(size_t)f * Kp + e] = (f < n_h) ? g.mu[k] : g.eps[k];
+        }
+        for (int n = 0; n < Np; ++n) {
+            X[(size_t)n * Kp + e] = g.x[(size_t)k * Np + n];
+            Y[(size_t)n * Kp + e] = g.y[(size_t)k * Np + n];
+            if (dim == 3) Z[(size_t)n * Kp + e] = g.z[(size_t)k * Np + n];
+        }
+        for (int f = 0; f < Nf; ++f) {
+            const size_t kf = (size_t)k * Nf + f;
+            const double *nrm = &g.normal[kf * dim];
+            const double Fs = g.sJ[kf] / g.J[k];
+            float *fg = &fgeo[(size_t)f * s->FG * Kp + e];
+            for (int c = 0; c < dim; ++c) fg[(size_t)c * Kp] = (float)nrm[c];
+            const int64_t k2 = g.nbr_elem[kf];
+            if (dim == 2 && s->material) {
+                // exact upwind (Riemann) flux across the face, blended by
+                // alpha with the central flux; Fscale/eps- and Fscale/mu- folded in
+                const double Zm = std::sqrt(g.mu[k] / g.eps[k]);
+                const double Zp = k2 >= 0 ? std::sqrt(g.mu[k2] / g.eps[k2]) : Zm;
+                const double sZ = Zm + Zp;
+                const double cEE = alpha / sZ, cEh = 0.5 * (1 - alpha) + alpha * Zp / sZ;
+                const double cHE = 0.5 * (1 - alpha) + alpha * Zm / sZ, cHh = alpha * Zm * Zp / sZ;
+                fg[(size_t)2 * Kp] = (float)(Fs / g.eps[k] * cEE);
+                fg[(size_t)3 * Kp] = (float)(Fs / g.eps[k] * cEh);
+                fg[(size_t)4 * Kp] = (float)(Fs / g.mu[k] * cHE);
+                fg[(size_t)5 * Kp] = (float)(Fs / g.mu[k] * cHh);
+            } else {
+                fg[(size_t)dim * Kp] = (float)Fs;
+            }
+            if (k2 >= 0) {
+                const int64_t e2 = s->iperm[k2];
+                nbr[(size_t)f * Kp + e] = int((e2 << 5) | (g.nbr_face[kf] << 3) | g.nbr_orient[kf]);
+            }
+        }
+    }
+    // operators and tables
+    std::vector<float> ops;
+    auto put = [&](const dgw::Mat &M) {
+        for (double v : M.a) ops.push_back((float)v);
+    };
+    put(R.Dr);
+    put(R.Ds);
+    if (dim == 3) put(R.Dt);
+    put(R.LIFT);
+    std::vector<int> itab(R.face_nodes.begin(), R.face_nodes.end());
+    for (int f2 = 0; f2 < Nf; ++f2)
+        for (int o = 0; o < R.n_orient; ++o)
+            for (int i = 0; i < Nfp; ++i) itab.push_back(R.face_nodes[f2 * Nfp + R.orient_perm[o * Nfp + i]]);
+    std::vector<int> permv(s->perm.begin(), s->perm.end());
+
+    if ((rc = dalloc(&s->geo_d, geo.size())) || (rc = dalloc(&s->fgeo_d, fgeo.size())) ||
+        (rc = dalloc(&s->nbr_d, nbr.size())) || (rc = dalloc(&s->ops_d, ops.size())) ||
+        (rc = dalloc(&s->itab_d, itab.size())) || (rc = dalloc(&s->perm_d, permv.size())) ||
+        (rc = dalloc(&s->J_d, J.size())) || (rc = dalloc(&s->M_d, R.M.a.size())) ||
+        (rc = dalloc(&s->x_d, X.size())) || (rc = dalloc(&s->y_d, Y.size())) ||
+        (rc = dalloc(&s->partial_d, 2 * kRedBlocks)))
+        return rc;
+    if (dim == 3 && (rc = dalloc(&s->z_d, Z.size()))) return rc;
+    if (s->material && (rc = dalloc(&s->w_d, w.size()))) return rc;
+    if ((rc = upload(s->geo_d, geo)) || (rc = upload(s->fgeo_d, fgeo)) || (rc = upload(s->nbr_d, nbr)) ||
+        (rc = upload(s->ops_d, ops)) || (rc = upload(s->itab_d, itab)) || (rc = upload(s->perm_d, permv)) ||
+        (rc = upload(s->J_d, J)) || (rc = upload(s->M_d, R.M.a)) || (rc = upload(s->x_d, X)) ||
+        (rc = upload(s->y_d, Y)))
+        return rc;
+    if (dim == 3 && (rc = upload(s->z_d, Z))) return rc;
+    if (s->material && (rc = upload(s->w_d, w))) return rc;
+    return DGW_OK;
+}
+
+int need_device(const dgw_solver *s) {
+    if (!s) return fail(DGW_EINVAL, "NULL solver");
+    if (!s->on_device) return fail(DGW_ENODEVICE, "solver was created host-only (device = -1)");
+    return DGW_OK;
+}
+
+int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) {
+    dgw::StageArgs a{};
+    a.res = s->res;
+    a.geo = s->geo_d;
+    a.fgeo = s->fgeo_d;
+    a.nbr = s->nbr_d;
+    a.ops = s->ops_d;
+    a.itab = s->itab_d;
+    a.Kp = (int)s->Kp;
+    a.ntiles = (int)(s->Kp / dgw::kTile);
+    a.dt = (float)dt;
+    a.alpha = (float)s->opts.alpha;
+    for (int64_t n = 0; n < nsteps; ++n)
+        for (int st5 = 0; st5 < 5; ++st5) {
+            a.qin = s->q[s->cur];
+            a.qout = s->q[1 - s->cur];
+            a.a = (float)kRkA[st5];
+            a.b = (float)kRkB[st5];
+            DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, a, st));
+            s->cur = 1 - s->cur;
+        }
+    return DGW_OK;
+}
+
+// caller-order FP64 [nf][K][Np] -> internal FP32 node-major upload into q[cur]
+int upload_fields(dgw_solver *s, const double *q) {
+    const int Np = s->Np, nf = s->nf;
+    const int64_t K = s->K, Kp = s->Kp;
+    std::vector<float> h((size_t)nf * Np * Kp, 0.0f);
+    for (int f = 0; f < nf; ++f)
+        for (int64_t e = 0; e < K; ++e) {
+            const int64_t k = s->perm[e];
+            const double *src = q + ((size_t)f * K + k) * Np;
+            for (int n = 0; n < Np; ++n) h[((size_t)f * Np + n) * Kp + e] = (float)src[n];
+        }
+    DGW_HIP(hipMemcpy(s->q[s->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    return DGW_OK;
+}
+
+int download(dgw_solver *s, const float *src_d, double *out) {
+    const int Np = s->Np, nf = s->nf;
+    const int64_t K = s->K, Kp = s->Kp;
+    std::vector<float> h((size_t)nf * Np * Kp);
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    DGW_HIP(hipMemcpy(h.data(), src_d, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int f = 0; f < nf; ++f)
+        for (int64_t e = 0; e < K; ++e) {
+            const int64_t k = s->perm[e];
+            double *dst = out + ((size_t)f * K + k) * Np;
+            for (int n = 0; n < Np; ++n) dst[n] = h[((size_t)f * Np + n) * Kp + e];
+        }
+    return DGW_OK;
+}
+
+double flops_per_element(int dim, int Np, int Nafp, int nf) {
+    if (dim == 2) {
+        // the paper's model (volume r,s derivatives of 3 fields, chain rule,
+        // lift incl. Jacobian, jumps + flux) plus 4 flops per DOF for the RK update
+        return 6.0 * 2 * Np * Np + 2.0 * Np * 13 + 3.0 * (2.0 * Np * Nafp + Np) + Nafp * 18.0 + 4.0 * nf * Np;
+    }
+    // 3D analogue: r,s,t derivatives of 6 fields, chain rule + curl (9 partials
+    // per field pair), lift of 6 fluxes, jumps + flux, RK update
+    return 18.0 * 2 * Np * Np + 2.0 * Np * 6 * 9 + 6.0 * (2.0 * Np * Nafp + Np) + Nafp * 60.0 + 4.0 * nf * Np;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dgw_strerror(int code) {
+    switch (code) {
+        case DGW_OK: return "ok";
+        case DGW_EINVAL: return "invalid argument";
+        case DGW_EMESH: return "invalid mesh";
+        case DGW_EORDER: return "unsupported order";
+        case DGW_ENOMEM: return "out of memory";
+        case DGW_ETOOBIG: return "footprint too large";
+        case DGW_EDEVICE: return "device (HIP) error";
+        case DGW_ENONFINITE: return "non-finite field";
+        case DGW_ECANCELLED: return "cancelled";
+        case DGW_ENOTFOUND: return "not found";
+        case DGW_ENODEVICE: return "no device for this handle";
+        default: return "unknown error";
+    }
+}
+
+const char *dgw_last_error(void) { return g_last_error.c_str(); }
+
+int dgw_opts_default(dgw_opts *o) {
+    if (!o) return fail(DGW_EINVAL, "NULL opts");
+    std::memset(o, 0, sizeof(*o));
+    o->alpha = 1.0;
+    o->cfl = 1.0;
+    o->prec = DGW_FP32;
+    o->renumber = 1;
+    o->device = 0;
+    return DGW_OK;
+}
+
+int dgw_reference_element(int32_t dim, int32_t order, int32_t *Np, int32_t *Nfp, double *r, double *s, double *t,
+                          double *Dr, double *Ds, double *Dt, double *M, double *LIFT, int32_t *face_nodes) {
+    try {
+        const dgw::RefElement R = dgw::make_ref_element(dim, order);
+        if (Np) *Np = R.Np;
+        if (Nfp) *Nfp = R.Nfp;
+        auto cp = [](double *d, const std::vector<double> &v) {
+            if (d) std::copy(v.begin(), v.end(), d);
+        };
+        cp(r, R.r);
+        cp(s, R.s);
+        if (dim == 3) cp(t, R.t);
+        cp(Dr, R.Dr.a);
+        cp(Ds, R.Ds.a);
+        if (dim == 3) cp(Dt, R.Dt.a);
+        cp(M, R.M.a);
+        cp(LIFT, R.LIFT.a);
+        if (face_nodes) std::copy(R.face_nodes.begin(), R.face_nodes.end(), face_nodes);
+        return DGW_OK;
+    } catch (const std::invalid_argument &e) {
+        return fail(dim == 2 || dim == 3 ? DGW_EORDER : DGW_EINVAL, e.what());
+    } catch (const std::exception &e) {
+        return fail(DGW_EINVAL, e.what());
+    }
+}
+
+int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw_solver **out) {
+    if (!out) return fail(DGW_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (!mesh) return fail(DGW_EINVAL, "NULL mesh");
+    if (mesh->dim != 2 && mesh->dim != 3) return fail(DGW_EINVAL, "dim must be 2 or 3");
+    if (mesh->n_elems <= 0 || mesh->n_verts <= 0) return fail(DGW_EINVAL, "empty mesh");
+    if (!mesh->vx || !mesh->vy || (mesh->dim == 3 && !mesh->vz) || !mesh->elem_verts)
+        return fail(DGW_EINVAL, "NULL mesh array");
+    if (order < 1 || order > (mesh->dim == 2 ? 8 : 6))
+        return fail(DGW_EORDER, "order must be in 1..8 (2D) or 1..6 (3D)");
+    if (mesh->n_elems >= (int64_t(1) << 26)) return fail(DGW_ETOOBIG, "more than 2^26 elements");
+    dgw_opts opts;
+    dgw_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.cfl <= 0) opts.cfl = 1.0;
+    if (!(opts.alpha >= 0.0 && opts.alpha <= 1.0)) return fail(DGW_EINVAL, "alpha must be in [0, 1]");
+    if (opts.prec != DGW_FP32) return fail(DGW_EINVAL, "precision variant not available in this build");
+    auto t0 = std::chrono::steady_clock::now();
+    dgw_solver *s = new (std::nothrow) dgw_solver();
+    if (!s) return fail(DGW_ENOMEM, "host allocation failed");
+    s->opts = opts;
+    s->dim = mesh->dim;
+    s->N = order;
+    try {
+        s->ref = dgw::make_ref_element(mesh->dim, order);
+        s->g = dgw::build_geometry(s->ref, mesh->dim, mesh->n_verts, mesh->vx, mesh->vy, mesh->vz, mesh->n_elems,
+                                   mesh->elem_verts, mesh->eps, mesh->mu);
+    } catch (const dgw::MeshError &e) {
+        delete s;
+        return fail(e.code == -1 ? DGW_EINVAL : DGW_EMESH, e.msg);
+    } catch (const std::bad_alloc &) {
+        delete s;
+        return fail(DGW_ENOMEM, "host allocation failed during set-up");
+    } catch (const std::exception &e) {
+        delete s;
+        return fail(DGW_EINVAL, e.what());
+    }
+    s->Np = s->ref.Np;
+    s->Nfp = s->ref.Nfp;
+    s->Nfaces = s->ref.Nfaces;
+    s->nf = s->dim == 2 ? 3 : 6;
+    s->K = mesh->n_elems;
+    s->Kp = (s->K + dgw::kTile - 1) / dgw::kTile * dgw::kTile;
+    for (int64_t k = 0; k < s->K; ++k)
+        if (s->g.eps[k] != 1.0 || s->g.mu[k] != 1.0) s->material = true;
+    if (s->dim == 3 && s->material) {
+        delete s;
+        return fail(DGW_EINVAL, "the 3D path supports eps = mu = 1 only");
+    }
+    s->G = s->dim == 2 ? (s->material ? 6 : 4) : 9;
+    s->FG = s->dim == 2 ? (s->material ? 6 : 3) : 4;
+    std::vector<int64_t> order_v;
+    if (opts.renumber)
+        order_v = dgw::morton_order(s->g);
+    else {
+        order_v.resize(s->K);
+        for (int64_t k = 0; k < s->K; ++k) order_v[k] = k;
+    }
+    s->perm.assign(order_v.begin(), order_v.end());
+    s->iperm.assign(s->K, 0);
+    for (int64_t e = 0; e < s->K; ++e) s->iperm[s->perm[e]] = (int)e;
+    s->dt_cfl = dgw::cfl_dt(s->ref, s->g, opts.cfl);
+    if (opts.device >= 0) {
+        int rc = setup_device(s);
+        if (rc != DGW_OK) {
+            free_device(s);
+            delete s;
+            return rc;
+        }
+    }
+    s->info.setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = s;
+    return DGW_OK;
+}
+
+void dgw_destroy(dgw_solver *s) {
+    if (!s) return;
+    free_device(s);
+    delete s;
+}
+
+int dgw_sizes(const dgw_solver *s, int64_t *K, int32_t *Np, int32_t *n_fields) {
+    if (!s) return fail(DGW_EINVAL, "NULL solver");
+    if (K) *K = s->K;
+    if (Np) *Np = s->Np;
+    if (n_fields) *n_fields = s->nf;
+    return DGW_OK;
+}
+
+int dgw_node_coords(const dgw_solver *s, double *x, double *y, double *z) {
+    if (!s) return fail(DGW_EINVAL, "NULL solver");
+    if (x) std::copy(s->g.x.begin(), s->g.x.end(), x);
+    if (y) std::copy(s->g.y.begin(), s->g.y.end(), y);
+    if (z && s->dim == 3) std::copy(s->g.z.begin(), s->g.z.end(), z);
+    return DGW_OK;
+}
+
+int dgw_cfl_dt(const dgw_solver *s, double *dt) {
+    if (!s || !dt) return fail(DGW_EINVAL, "NULL argument");
+    *dt = s->dt_cfl;
+    return DGW_OK;
+}
+
+int dgw_set_fields(dgw_solver *s, const double *q) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!q) return fail(DGW_EINVAL, "NULL fields");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    if ((rc = upload_fields(s, q))) return rc;
+    DGW_HIP(hipMemset(s->res, 0, (size_t)s->nf * s->Np * s->Kp * sizeof(float)));
+    s->t = 0.0;
+    return DGW_OK;
+}
+
+int dgw_get_fields(dgw_solver *s, double *q) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!q) return fail(DGW_EINVAL, "NULL fields");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    return download(s, s->q[s->cur], q);
+}
+
+int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!mode) return fail(DGW_EINVAL, "NULL mode");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    dgw::CavityArgs a{};
+    a.q = s->q[s->cur];
+    a.x = s->x_d;
+    a.y = s->y_d;
+    a.z = s->z_d;
+    a.Kp = (int)s->Kp;
+    a.K = (int)s->K;
+    a.Np = s->Np;
+    a.dim = s->dim;
+    a.m = mode[0];
+    a.n = mode[1];
+    a.l = s->dim == 3 ? mode[2] : 0;
+    a.eps = s->g.eps[0];
+    a.mu = s->g.mu[0];
+    a.t = 0.0;
+    DGW_HIP(dgw::launch_cavity_init(a, s->stream));
+    DGW_HIP(hipMemsetAsync(s->res, 0, (size_t)s->nf * s->Np * s->Kp * sizeof(float), s->stream));
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    s->t = 0.0;
+    return DGW_OK;
+}
+
+int dgw_advance_steps(dgw_solver *s, int64_t nsteps, double dt) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(DGW_EINVAL, "negative step count");
+    if (dt <= 0) dt = s->dt_cfl;
+    DGW_HIP(hipSetDevice(s->opts.device));
+    DGW_HIP(hipEventRecord(s->ev0, s->stream));
+    if ((rc = launch_steps_impl(s, nsteps, dt, s->stream))) return rc;
+    DGW_HIP(hipEventRecord(s->ev1, s->stream));
+    DGW_HIP(hipEventSynchronize(s->ev1));
+    float ms = 0.0f;
+    DGW_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->t += nsteps * dt;
+    s->info.steps = nsteps;
+    s->info.dt = dt;
+    s->info.t = s->t;
+    s->info.solve_ms = ms;
+    s->info.dof_updates_per_s = ms > 0 ? double(s->nf) * s->K * s->Np * nsteps / (ms * 1e-3) : 0.0;
+    return DGW_OK;
+}
+
+int dgw_advance(dgw_solver *s, double t_final, double dt, int64_t *steps_taken) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!(t_final >= 0)) return fail(DGW_EINVAL, "t_final must be >= 0");
+    int64_t n;
+    if (dt <= 0) {
+        n = (int64_t)std::ceil(t_final / s->dt_cfl - 1e-12);
+        if (n < 1) n = 1;
+        dt = t_final / n;
+    } else {
+        n = (int64_t)std::llround(t_final / dt);
+    }
+    if (t_final == 0) n = 0;
+    if ((rc = dgw_advance_steps(s, n, dt))) return rc;
+    if (steps_taken) *steps_taken = n;
+    return DGW_OK;
+}
+
+int dgw_rhs(dgw_solver *s, const double *q, double *rhs) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!q || !rhs) return fail(DGW_EINVAL, "NULL argument");
+    if ((rc = dgw_set_fields(s, q))) return rc;
+    dgw::StageArgs a{};
+    a.qin = s->q[s->cur];
+    a.qout = s->q[1 - s->cur];
+    a.res = s->res;
+    a.geo = s->geo_d;
+    a.fgeo = s->fgeo_d;
+    a.nbr = s->nbr_d;
+    a.ops = s->ops_d;
+    a.itab = s->itab_d;
+    a.Kp = (int)s->Kp;
+    a.ntiles = (int)(s->Kp / dgw::kTile);
+    a.a = 0.0f;
+    a.b = 0.0f;
+    a.dt = 1.0f;
+    a.alpha = (float)s->opts.alpha;
+    DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, a, s->stream));
+    s->cur = 1 - s->cur;
+    return download(s, s->res, rhs);
+}
+
+int dgw_energy(dgw_solver *s, double *energy) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!energy) return fail(DGW_EINVAL, "NULL output");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    dgw::ReduceArgs a{};
+    a.q = s->q[s->cur];
+    a.J = s->J_d;
+    a.Mref = s->M_d;
+    a.w = s->w_d;
+    a.Kp = (int)s->Kp;
+    a.K = (int)s->K;
+    a.Np = s->Np;
+    a.nf = s->nf;
+    a.partial = s->partial_d;
+    DGW_HIP(dgw::launch_energy(a, kRedBlocks, s->stream));
+    std::vector<double> h(kRedBlocks);
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    DGW_HIP(hipMemcpy(h.data(), s->partial_d, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost));
+    double e = 0.0;
+    for (double v : h) e += v;
+    *energy = 0.5 * e;
+    if (!std::isfinite(*energy)) return fail(DGW_ENONFINITE, "energy is not finite");
+    return DGW_OK;
+}
+
+int dgw_cavity_error(dgw_solver *s, const int32_t mode[3], double t, double *rel_l2) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!mode || !rel_l2) return fail(DGW_EINVAL, "NULL argument");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    dgw::CavityArgs a{};
+    a.q = s->q[s->cur];
+    a.x = s->x_d;
+    a.y = s->y_d;
+    a.z = s->z_d;
+    a.J = s->J_d;
+    a.Mref = s->M_d;
+    a.Kp = (int)s->Kp;
+    a.K = (int)s->K;
+    a.Np = s->Np;
+    a.dim = s->dim;
+    a.m = mode[0];
+    a.n = mode[1];
+    a.l = s->dim == 3 ? mode[2] : 0;
+    a.eps = s->g.eps[0];
+    a.mu = s->g.mu[0];
+    a.t = t;
+    a.partial = s->partial_d;
+    DGW_HIP(dgw::launch_cavity_error(a, kRedBlocks, s->stream));
+    std::vector<double> h(2 * kRedBlocks);
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    DGW_HIP(hipMemcpy(h.data(), s->partial_d, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double num = 0.0, den = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) {
+        num += h[2 * b];
+        den += h[2 * b + 1];
+    }
+    *rel_l2 = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+    if (!std::isfinite(*rel_l2)) return fail(DGW_ENONFINITE, "error is not finite");
+    return DGW_OK;
+}
+
+int dgw_last_info(const dgw_solver *s, dgw_info *info) {
+    if (!s || !info) return fail(DGW_EINVAL, "NULL argument");
+    *info = s->info;
+    return DGW_OK;
+}
+
+int dgw_set_fields_dev(dgw_solver *s, const float *q_dev, void *stream) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!q_dev) return fail(DGW_EINVAL, "NULL fields");
+    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    DGW_HIP(hipSetDevice(s->opts.device));
+    DGW_HIP(dgw::launch_to_internal(q_dev, s->q[s->cur], s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf, st));
+    DGW_HIP(hipMemsetAsync(s->res, 0, (size_t)s->nf * s->Np * s->Kp * sizeof(float), st));
+    s->t = 0.0;
+    return DGW_OK;
+}
+
+int dgw_get_fields_dev(dgw_solver *s, float *q_dev, void *stream) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!q_dev) return fail(DGW_EINVAL, "NULL fields");
+    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    DGW_HIP(hipSetDevice(s->opts.device));
+    DGW_HIP(dgw::launch_to_caller(s->q[s->cur], q_dev, s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf, st));
+    return DGW_OK;
+}
+
+int dgw_launch_steps(dgw_solver *s, int64_t nsteps, double dt, void *stream) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (nsteps < 0 || !(dt > 0)) return fail(DGW_EINVAL, "nsteps >= 0 and dt > 0 required");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    if ((rc = launch_steps_impl(s, nsteps, dt, st))) return rc;
+    s->t += nsteps * dt;
+    return DGW_OK;
+}
+
+int dgw_stage_cost(const dgw_solver *s, double *bytes, double *flops) {
+    if (!s) return fail(DGW_EINVAL, "NULL solver");
+    const int Nafp = s->Nfaces * s->Nfp;
+    // algorithmic HBM traffic per element: read q_in and res, write res and
+    // q_out (4 words per DOF) plus the per-element and per-face factors and
+    // the face records
+    const double per_el = 16.0 * s->nf * s->Np + 4.0 * s->G + s->Nfaces * (4.0 * s->FG + 4.0);
+    if (bytes) *bytes = per_el * double(s->K);
+    if (flops) *flops = flops_per_element(s->dim, s->Np, Nafp, s->nf) * double(s->K);
+    return DGW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+// Fused LSRK stage for 2D TM Maxwell on triangles, FP32, gfx950.
+//
+// One work-group (4 waves) owns a tile of 64 consecutive elements; lane l of
+// every wave works on element tile*64 + l, so every global access to the
+// node-major fields is a 256-byte contiguous row.  Per stage it computes the
+// semi-discrete right-hand side of eq. dg-strong-explicit and the 2N-storage
+// RK update in one pass over HBM:
+//   1. stage the tile's fields q_in (3 x Np x 64) in LDS;
+//   2. face gather + upwind flux (eq. max2d-numflux with the factor 1/2,
+//      [q] = q^- - q^+; PEC mirror state on the wall; exact Riemann flux across
+//      eps/mu jumps): wave w takes face nodes w, w+4, ...; own traces come from
+//      LDS, the partner's from q_in in HBM/L2 through the compressed face
+//      record (partner element, face, orientation) and a small partner-node
+//      table; the scaled fluxes go to LDS;
+//   3. local differentiation: wave w takes output nodes w, w+4, ... and
+//      accumulates Dr q and Ds q for the three fields; the operator entries
+//      are wave-uniform, so they are fetched by scalar loads and feed the FMAs
+//      as scalar operands; the chain rule (eq. dg-diff-local-to-global)
+//      forms -dEz/dy, dEz/dx, dHy/dx - dHx/dy;
+//   4. LIFT apply of the LDS fluxes (eq. dg-lift), same operand scheme;
+//   5. res <- a res + dt rhs;  q_out <- q_in + b res  (res prefetched in 1.).
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace dgw {
+
+// Blocks are dispatched round-robin over the 8 XCDs of MI355X; give each XCD
+// a contiguous range of tiles so that neighbour traces are shared in its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <int N, bool MAT>
+__global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
+    constexpr int Np = (N + 1) * (N + 2) / 2;
+    constexpr int Nfp = N + 1;
+    constexpr int Nafp = 3 * Nfp;
+    constexpr int NW = 4;
+    constexpr int R = (Np + NW - 1) / NW;
+    constexpr int FG = MAT ? 6 : 3;
+    constexpr int TE = kTile;
+
+    __shared__ float sq[3 * Np * TE];
+    __shared__ float sf[3 * Nafp * TE];
+    __shared__ int stab[3 * 2 * Nfp];
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int Kp = A.Kp;
+    const int e = tile * TE + lane;
+
+    for (int i = threadIdx.x; i < 3 * 2 * Nfp; i += 256) stab[i] = A.itab[Nafp + i];
+
+    // 1. fields of the tile into LDS; prefetch this wave's residual entries
+#pragma unroll
+    for (int row = w; row < 3 * Np; row += NW) sq[row * TE + lane] = A.qin[(size_t)row * Kp + e];
+    float rres[3][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) rres[f][r] = A.res[(size_t)(f * Np + n) * Kp + e];
+    }
+    __syncthreads();
+
+    // 2. face gather and flux
+#pragma unroll
+    for (int j = w; j < Nafp; j += NW) {
+        const int face = j / Nfp, i = j - face * Nfp;
+        const int own = A.itab[j];
+        const float mHx = sq[(0 * Np + own) * TE + lane];
+        const float mHy = sq[(1 * Np + own) * TE + lane];
+        const float mEz = sq[(2 * Np + own) * TE + lane];
+        const int rec = A.nbr[face * Kp + e];
+        float pHx, pHy, pEz;
+        if (rec < 0) {  // PEC wall: mirror state E+ = -E-, H+ = H-
+            pHx = mHx;
+            pHy = mHy;
+            pEz = -mEz;
+        } else {
+            const int e2 = rec >> 5, f2 = (rec >> 3) & 3, o = rec & 7;
+            const int pn = stab[(f2 * 2 + o) * Nfp + i];
+            pHx = A.qin[(size_t)(0 * Np + pn) * Kp + e2];
+            pHy = A.qin[(size_t)(1 * Np + pn) * Kp + e2];
+            pEz = A.qin[(size_t)(2 * Np + pn) * Kp + e2];
+        }
+        const float *fg = A.fgeo + (size_t)face * FG * Kp + e;
+        const float nx = fg[0], ny = fg[(size_t)Kp];
+        const float dHx = mHx - pHx, dHy = mHy - pHy, dEz = mEz - pEz;
+        const float dh = nx * dHy - ny * dHx;  // jump of the tangential field
+        float cEE, cEh, cHE, cHh;
+        if (MAT) {
+            cEE = fg[2 * (size_t)Kp];
+            cEh = fg[3 * (size_t)Kp];
+            cHE = fg[4 * (size_t)Kp];
+            cHh = fg[5 * (size_t)Kp];
+        } else {
+            const float hs = 0.5f * fg[2 * (size_t)Kp];
+            cEE = A.alpha * hs;
+            cEh = hs;
+            cHE = hs;
+            cHh = A.alpha * hs;
+        }
+        const float fE = -(cEE * dEz + cEh * dh);
+        const float fH = cHE * dEz + cHh * dh;
+        sf[(0 * Nafp + j) * TE + lane] = ny * fH;
+        sf[(1 * Nafp + j) * TE + lane] = -nx * fH;
+        sf[(2 * Nafp + j) * TE + lane] = fE;
+    }
+    __syncthreads();
+
+    // 3. local differentiation of the three fields for this wave's nodes
+    const float *Dr = A.ops;
+    const float *Ds = A.ops + Np * Np;
+    const float *L = A.ops + 2 * Np * Np;
+    float ar[3][R], as[3][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) ar[f][r] = as[f][r] = 0.f;
+#pragma unroll
+    for (int jn = 0; jn < Np; ++jn) {
+        const float v0 = sq[(0 * Np + jn) * TE + lane];
+        const float v1 = sq[(1 * Np + jn) * TE + lane];
+        const float v2 = sq[(2 * Np + jn) * TE + lane];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
+            const float cr = Dr[n * Np + jn], cs = Ds[n * Np + jn];
+            ar[0][r] += cr * v0;
+            as[0][r] += cs * v0;
+            ar[1][r] += cr * v1;
+            as[1][r] += cs * v1;
+            ar[2][r] += cr * v2;
+            as[2][r] += cs * v2;
+        }
+    }
+    const float rx = A.geo[e], ry = A.geo[(size_t)Kp + e];
+    const float sx = A.geo[2 * (size_t)Kp + e], sy = A.geo[3 * (size_t)Kp + e];
+    float rhs[3][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        rhs[0][r] = -(ry * ar[2][r] + sy * as[2][r]);
+        rhs[1][r] = rx * ar[2][r] + sx * as[2][r];
+        rhs[2][r] = (rx * ar[1][r] + sx * as[1][r]) - (ry * ar[0][r] + sy * as[0][r]);
+    }
+    if (MAT) {
+        const float ieps = A.geo[4 * (size_t)Kp + e], imu = A.geo[5 * (size_t)Kp + e];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            rhs[0][r] *= imu;
+            rhs[1][r] *= imu;
+            rhs[2][r] *= ieps;
+        }
+    }
+
+    // 4. LIFT apply
+#pragma unroll
+    for (int j = 0; j < Nafp; ++j) {
+        const float f0 = sf[(0 * Nafp + j) * TE + lane];
+        const float f1 = sf[(1 * Nafp + j) * TE + lane];
+        const float f2 = sf[(2 * Nafp + j) * TE + lane];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
+            const float c = L[n * Nafp + j];
+            rhs[0][r] += c * f0;
+            rhs[1][r] += c * f1;
+            rhs[2][r] += c * f2;
+        }
+    }
+
+    // 5. fused low-storage RK update
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int n = w + NW * r;
+        if (n < Np) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const size_t idx = (size_t)(f * Np + n) * Kp + e;
+                const float rr = A.a * rres[f][r] + A.dt * rhs[f][r];
+                A.res[idx] = rr;
+                A.qout[idx] = sq[(f * Np + n) * TE + lane] + A.b * rr;
+            }
+        }
+    }
+}
+
+template <int N, bool MAT>
+static hipError_t launch2d(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((stage2d_kernel<N, MAT>), dim3(a.ntiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage3d(int N, const StageArgs &args, hipStream_t stream);
+const char *stage3d_kernel_name(int N);
+
+hipError_t launch_stage(int dim, int N, bool material, const StageArgs &a, hipStream_t s) {
+    if (dim == 3) return launch_stage3d(N, a, s);
+#define DGW_CASE(n)                                                    \
+    case n:                                                            \
+        return material ? launch2d<n, true>(a, s) : launch2d<n, false>(a, s);
+    switch (N) {
+        DGW_CASE(1)
+        DGW_CASE(2)
+        DGW_CASE(3)
+        DGW_CASE(4)
+        DGW_CASE(5)
+        DGW_CASE(6)
+        DGW_CASE(7)
+        DGW_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef DGW_CASE
+}
+
+const char *stage_kernel_name(int dim, int N, bool material) {
+    (void)N;
+    if (dim == 3) return stage3d_kernel_name(N);
+    return material ? "stage2d_kernel<N, true>" : "stage2d_kernel<N, false>";
+}
+
+}  // namespace dgw
