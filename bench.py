@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--kernel", type=int, default=0, help="stage kernel: 0 auto, 1 scalar-operand VALU, 2 MFMA")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU halo exchange is design-only",
@@ -91,7 +92,7 @@ def main():
     s_grid, seed, permute, N, mode, desc = CONFIGS[args.config]
     mesh = inputs.tri_grid(s_grid, seed=seed, permute=permute)
     stream = torch.cuda.Stream()
-    solver = dgw.Solver(mesh, N, stream=stream)
+    solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel)
     dt = solver.cfl_dt()
     solver.set_cavity_mode(*mode)
     bytes_per_launch, flops_per_launch = solver.stage_cost()
@@ -131,7 +132,8 @@ def main():
         "gflops_paper_model": flops_per_launch / launch_s / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"stage2d_kernel<{N}, false>", "avg_launch_us": launch_s * 1e6,
+                     "kernel": (f"stage2d_kernel<{N}, false>" if args.kernel == 1
+                                else f"stage2d_mfma_kernel<{N}, false>"), "avg_launch_us": launch_s * 1e6,
                      "bytes_per_launch": bytes_per_launch},
     }
     solver.close()

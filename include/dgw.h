@@ -93,7 +93,7 @@ typedef struct {
     int32_t prec;        /* dgw_precision                                         */
     int32_t renumber;    /* 1 (default): space-filling-curve element order on GPU */
     int32_t device;      /* HIP device ordinal; -1 = host-only handle (setup only)*/
-    int32_t reserved;
+    int32_t kernel;      /* stage kernel: 0 auto (MFMA), 1 scalar-operand VALU, 2 MFMA */
     void *hip_stream;    /* hipStream_t to launch on; NULL = library's own stream */
 } dgw_opts;
 

@@ -35,12 +35,12 @@ __global__ void __launch_bounds__(kRedThreads) energy_kernel(ReduceArgs a) {
         for (int f = 0; f < a.nf; ++f) {
             double qf = 0.0;
             for (int i = 0; i < a.Np; ++i) {
-                const double qi = a.q[(size_t)(f * a.Np + i) * a.Kp + e];
+                const double qi = a.q[tix(e, f * a.Np + i, a.nf * a.Np)];
                 double mq = 0.0;
-                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * (double)a.q[(size_t)(f * a.Np + j) * a.Kp + e];
+                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * (double)a.q[tix(e, f * a.Np + j, a.nf * a.Np)];
                 qf += qi * mq;
             }
-            ek += (a.w ? a.w[(size_t)f * a.Kp + e] : 1.0) * qf;
+            ek += (a.w ? a.w[tix(e, f, a.nf)] : 1.0) * qf;
         }
         acc += a.J[e] * ek;
     }
@@ -87,10 +87,10 @@ __global__ void cavity_init_kernel(CavityArgs a) {
     for (int i = 0; i < a.Np; ++i) {
         double out[6] = {0, 0, 0, 0, 0, 0};
         if (e < a.K) {
-            const size_t p = (size_t)i * a.Kp + e;
+            const size_t p = tix(e, i, a.Np);
             cavity_exact(a, a.x[p], a.y[p], a.dim == 3 ? a.z[p] : 0.0, out);
         }
-        for (int f = 0; f < nf; ++f) a.q[(size_t)(f * a.Np + i) * a.Kp + e] = (float)out[f];
+        for (int f = 0; f < nf; ++f) a.q[tix(e, f * a.Np + i, nf * a.Np)] = (float)out[f];
     }
 }
 
@@ -104,17 +104,17 @@ __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a)
     for (int e = blockIdx.x * kRedThreads + threadIdx.x; e < a.K; e += gridDim.x * kRedThreads) {
         double nk = 0.0, dk = 0.0;
         for (int i = 0; i < a.Np; ++i) {
-            const size_t pi = (size_t)i * a.Kp + e;
+            const size_t pi = tix(e, i, a.Np);
             double exi[6], di[6], md[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
             cavity_exact(a, a.x[pi], a.y[pi], a.dim == 3 ? a.z[pi] : 0.0, exi);
-            for (int f = 0; f < nf; ++f) di[f] = (double)a.q[(size_t)(f * a.Np + i) * a.Kp + e] - exi[f];
+            for (int f = 0; f < nf; ++f) di[f] = (double)a.q[tix(e, f * a.Np + i, nf * a.Np)] - exi[f];
             for (int j = 0; j < a.Np; ++j) {
-                const size_t pj = (size_t)j * a.Kp + e;
+                const size_t pj = tix(e, j, a.Np);
                 double exj[6];
                 cavity_exact(a, a.x[pj], a.y[pj], a.dim == 3 ? a.z[pj] : 0.0, exj);
                 const double Mij = a.Mref[i * a.Np + j];
                 for (int f = 0; f < nf; ++f) {
-                    md[f] += Mij * ((double)a.q[(size_t)(f * a.Np + j) * a.Kp + e] - exj[f]);
+                    md[f] += Mij * ((double)a.q[tix(e, f * a.Np + j, nf * a.Np)] - exj[f]);
                     mx[f] += Mij * exj[f];
                 }
             }
@@ -137,9 +137,10 @@ __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a)
 __global__ void to_internal_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf) {
     const size_t total = (size_t)nf * Np * Kp;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        const int e = int(t % Kp);
-        const size_t fn = t / Kp;
-        const int n = int(fn % Np), f = int(fn / Np);
+        const int rows = nf * Np;
+        const int e = int((t / ((size_t)64 * rows)) * 64 + (t & 63));
+        const int row = int((t / 64) % rows);
+        const int n = row % Np, f = row / Np;
         dst[t] = e < K ? src[((size_t)f * K + perm[e]) * Np + n] : 0.0f;
     }
 }
@@ -150,7 +151,7 @@ __global__ void to_caller_kernel(const float *src, float *dst, const int *perm, 
         const int e = int(t % K);
         const size_t fn = t / K;
         const int n = int(fn % Np), f = int(fn / Np);
-        dst[((size_t)f * K + perm[e]) * Np + n] = src[(size_t)(f * Np + n) * Kp + e];
+        dst[((size_t)f * K + perm[e]) * Np + n] = src[tix(e, f * Np + n, nf * Np)];
     }
 }
 

@@ -1,16 +1,17 @@
 // Device-side data layout and launch wrappers of the fused LSRK stage.
 //
 // HBM layout (internal element order e = 0..Kp-1, Kp = K rounded up to the
-// 64-element tile; padding elements carry zero fields and geometry):
-//   q, res  : [n_fields][Np][Kp] FP32, node-major so that one wave's 64 lanes
-//             (64 consecutive elements of a tile) read one node of one field
-//             as 256 contiguous bytes
-//   geo     : [G][Kp] FP32 per-element factors: 2D r_x, r_y, s_x, s_y
-//             (+ 1/eps, 1/mu with materials); 3D the nine entries of A_k^{-1}
-//   fgeo    : [Nfaces][FG][Kp] FP32 per-face data: 2D n_x, n_y, Fscale, or
-//             n_x, n_y and four flux coefficients with materials; 3D n_x,
-//             n_y, n_z, Fscale
-//   nbr     : [Nfaces][Kp] int32 face record: -1 on the PEC wall, else
+// 64-element tile; padding elements carry zero fields and geometry).  Every
+// per-element array is tiled, [tile][row][64] (see tix()), so that one wave's
+// 64 lanes (64 consecutive elements of a tile) read one row as 256
+// contiguous bytes:
+//   q, res  : rows f*Np + n, FP32 (n_fields*Np rows)
+//   geo     : G rows of per-element factors: 2D r_x, r_y, s_x, s_y (+ 1/eps,
+//             1/mu with materials); 3D the nine entries of A_k^{-1}
+//   fgeo    : Nfaces*FG rows of per-face data, row face*FG + q: 2D n_x, n_y,
+//             Fscale, or n_x, n_y and four flux coefficients with materials;
+//             3D n_x, n_y, n_z, Fscale
+//   nbr     : Nfaces rows of int32 face records: -1 on the PEC wall, else
 //             (e' << 5) | (f' << 3) | orientation
 //   ops     : FP32 Dr, Ds (, Dt) [Np][Np] and LIFT [Np][Nfaces*Nfp], row-major
 //   itab    : int32 own face nodes [Nfaces*Nfp], then the partner node table
@@ -25,6 +26,14 @@ namespace dgw {
 
 constexpr int kTile = 64;  // elements per work-group tile (one per lane)
 
+// Tiled (AoSoA) index of row `row` of element e in an array with `rows` rows
+// per element: [tile][row][64 elements].  One row of a tile is 256 contiguous
+// bytes (a coalesced wave access) and all rows of a tile form one contiguous
+// chunk, so a tile touches few pages whatever the mesh size.
+__host__ __device__ inline size_t tix(int64_t e, int row, int rows) {
+    return ((size_t)(e >> 6) * rows + row) * 64 + (size_t)(e & 63);
+}
+
 struct StageArgs {
     const float *qin;
     float *qout;
@@ -33,15 +42,28 @@ struct StageArgs {
     const float *fgeo;
     const int *nbr;
     const float *ops;
+    const float *opsfrag;  // fused operator in MFMA A-fragment order (2D MFMA kernel)
     const int *itab;
     int Kp;
     int ntiles;
+    int ngroups;  // work-groups of a persistent launch (multiple of 8)
     float a, b, dt, alpha;
 };
 
+// Kernel variants of the fused stage.
+enum StageVariant { kVariantAuto = 0, kVariantScalarOperand = 1, kVariantMfma = 2 };
+
 // Launch one fused stage: res <- a res + dt L(qin); qout <- qin + b res.
-hipError_t launch_stage(int dim, int N, bool material, const StageArgs &args, hipStream_t stream);
-const char *stage_kernel_name(int dim, int N, bool material);
+hipError_t launch_stage(int dim, int N, bool material, int variant, const StageArgs &args, hipStream_t stream);
+const char *stage_kernel_name(int dim, int N, bool material, int variant);
+
+hipError_t launch_stage2d_mfma(int N, bool material, const StageArgs &a, hipStream_t s);
+// fragment-ordered fused operator [Dr | Ds | LIFT] (see stage2d_mfma.hip);
+// with out == nullptr returns the required length
+int opsfrag2d(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
+int face_node2d(int N, int f, int t);
+// resident work-groups per CU of the persistent 2D MFMA kernel
+int blocks_per_cu_2d_mfma(int N, bool material);
 
 // FP64 reductions: per-block partial sums of
 //   energy: J_k sum_f w_f q_f^T M q_f     (w from wvec: [n_fields][Kp] FP64 or NULL = 1)

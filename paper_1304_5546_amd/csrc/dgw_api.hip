@@ -52,13 +52,14 @@ struct dgw_solver {
     std::vector<int> perm;   // internal e -> caller k
     std::vector<int> iperm;  // caller k -> internal e
     double dt_cfl = 0.0;
+    int ngroups = 8;  // persistent grid size
     bool on_device = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     float *q[2] = {nullptr, nullptr};
     float *res = nullptr;
     int cur = 0;
-    float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr;
+    float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr, *opsfrag_d = nullptr;
     int *nbr_d = nullptr, *itab_d = nullptr, *perm_d = nullptr;
     double *J_d = nullptr, *M_d = nullptr, *w_d = nullptr, *x_d = nullptr, *y_d = nullptr, *z_d = nullptr;
     double *partial_d = nullptr;
@@ -87,7 +88,7 @@ int upload(T *dst, const std::vector<T> &src) {
 void free_device(dgw_solver *s) {
     if (!s->on_device) return;
     hipSetDevice(s->opts.device);
-    void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->nbr_d, s->itab_d, s->perm_d,
+    void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->opsfrag_d, s->nbr_d, s->itab_d, s->perm_d,
                     s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -130,28 +131,29 @@ int setup_device(dgw_solver *s) {
     for (int64_t e = 0; e < K; ++e) {
         const int64_t k = s->perm[e];
         const double *D = &g.drst[(size_t)k * dim * dim];
-        for (int c = 0; c < dim * dim; ++c) geo[(size_t)c * Kp + e] = (float)D[c];
+        for (int c = 0; c < dim * dim; ++c) geo[dgw::tix(e, c, s->G)] = (float)D[c];
         if (dim == 2 && s->material) {
-            geo[(size_t)4 * Kp + e] = (float)(1.0 / g.eps[k]);
-            geo[(size_t)5 * Kp + e] = (float)(1.0 / g.mu[k]);
+            geo[dgw::tix(e, 4, s->G)] = (float)(1.0 / g.eps[k]);
+            geo[dgw::tix(e, 5, s->G)] = (float)(1.0 / g.mu[k]);
         }
         J[e] = g.J[k];
         if (s->material) {
             // magnetic fields (Hx, Hy[, Hz]) weigh with mu, electric ones with eps
             const int n_h = dim == 2 ? 2 : 3;
-            for (int f = 0; f < nf; ++f) w[(size_t)f * Kp + e] = (f < n_h) ? g.mu[k] : g.eps[k];
+            for (int f = 0; f < nf; ++f) w[dgw::tix(e, f, nf)] = (f < n_h) ? g.mu[k] : g.eps[k];
         }
         for (int n = 0; n < Np; ++n) {
-            X[(size_t)n * Kp + e] = g.x[(size_t)k * Np + n];
-            Y[(size_t)n * Kp + e] = g.y[(size_t)k * Np + n];
-            if (dim == 3) Z[(size_t)n * Kp + e] = g.z[(size_t)k * Np + n];
+            X[dgw::tix(e, n, Np)] = g.x[(size_t)k * Np + n];
+            Y[dgw::tix(e, n, Np)] = g.y[(size_t)k * Np + n];
+            if (dim == 3) Z[dgw::tix(e, n, Np)] = g.z[(size_t)k * Np + n];
         }
         for (int f = 0; f < Nf; ++f) {
             const size_t kf = (size_t)k * Nf + f;
             const double *nrm = &g.normal[kf * dim];
             const double Fs = g.sJ[kf] / g.J[k];
-            float *fg = &fgeo[(size_t)f * s->FG * Kp + e];
-            for (int c = 0; c < dim; ++c) fg[(size_t)c * Kp] = (float)nrm[c];
+            // rows face*FG + q of this element are 64 apart in the tiled layout
+            float *fg = &fgeo[dgw::tix(e, f * s->FG, Nf * s->FG)];
+            for (int c = 0; c < dim; ++c) fg[(size_t)c * 64] = (float)nrm[c];
             const int64_t k2 = g.nbr_elem[kf];
             if (dim == 2 && s->material) {
                 // exact upwind (Riemann) flux across the face, blended by
@@ -161,16 +163,16 @@ int setup_device(dgw_solver *s) {
                 const double sZ = Zm + Zp;
                 const double cEE = alpha / sZ, cEh = 0.5 * (1 - alpha) + alpha * Zp / sZ;
                 const double cHE = 0.5 * (1 - alpha) + alpha * Zm / sZ, cHh = alpha * Zm * Zp / sZ;
-                fg[(size_t)2 * Kp] = (float)(Fs / g.eps[k] * cEE);
-                fg[(size_t)3 * Kp] = (float)(Fs / g.eps[k] * cEh);
-                fg[(size_t)4 * Kp] = (float)(Fs / g.mu[k] * cHE);
-                fg[(size_t)5 * Kp] = (float)(Fs / g.mu[k] * cHh);
+                fg[(size_t)2 * 64] = (float)(Fs / g.eps[k] * cEE);
+                fg[(size_t)3 * 64] = (float)(Fs / g.eps[k] * cEh);
+                fg[(size_t)4 * 64] = (float)(Fs / g.mu[k] * cHE);
+                fg[(size_t)5 * 64] = (float)(Fs / g.mu[k] * cHh);
             } else {
-                fg[(size_t)dim * Kp] = (float)Fs;
+                fg[(size_t)dim * 64] = (float)Fs;
             }
             if (k2 >= 0) {
                 const int64_t e2 = s->iperm[k2];
-                nbr[(size_t)f * Kp + e] = int((e2 << 5) | (g.nbr_face[kf] << 3) | g.nbr_orient[kf]);
+                nbr[dgw::tix(e, f, Nf)] = int((e2 << 5) | (g.nbr_face[kf] << 3) | g.nbr_orient[kf]);
             }
         }
     }
@@ -188,14 +190,36 @@ int setup_device(dgw_solver *s) {
         for (int o = 0; o < R.n_orient; ++o)
             for (int i = 0; i < Nfp; ++i) itab.push_back(R.face_nodes[f2 * Nfp + R.orient_perm[o * Nfp + i]]);
     std::vector<int> permv(s->perm.begin(), s->perm.end());
+    std::vector<float> opsfrag;
+    if (dim == 2) {
+        // the MFMA kernel indexes face nodes in closed form: confirm it matches
+        for (int f = 0; f < Nf; ++f)
+            for (int i = 0; i < Nfp; ++i)
+                if (dgw::face_node2d(s->N, f, i) != R.face_nodes[f * Nfp + i])
+                    return fail(DGW_EINVAL, "internal: face node order mismatch");
+        opsfrag.resize(dgw::opsfrag2d(s->N, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag2d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
+    }
 
     if ((rc = dalloc(&s->geo_d, geo.size())) || (rc = dalloc(&s->fgeo_d, fgeo.size())) ||
         (rc = dalloc(&s->nbr_d, nbr.size())) || (rc = dalloc(&s->ops_d, ops.size())) ||
         (rc = dalloc(&s->itab_d, itab.size())) || (rc = dalloc(&s->perm_d, permv.size())) ||
         (rc = dalloc(&s->J_d, J.size())) || (rc = dalloc(&s->M_d, R.M.a.size())) ||
         (rc = dalloc(&s->x_d, X.size())) || (rc = dalloc(&s->y_d, Y.size())) ||
-        (rc = dalloc(&s->partial_d, 2 * kRedBlocks)))
+        (rc = dalloc(&s->partial_d, 2 * kRedBlocks)) || (rc = dalloc(&s->opsfrag_d, opsfrag.size())))
         return rc;
+    if (!opsfrag.empty() && (rc = upload(s->opsfrag_d, opsfrag))) return rc;
+    // persistent grid: every CU filled to its occupancy, a multiple of the 8
+    // XCDs, no more groups than tiles (rounded up to the 8 XCDs)
+    {
+        int ncu = 0;
+        DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
+        const int per_cu = dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material) : 1;
+        const int ntiles = (int)(Kp / dgw::kTile);
+        int ng = std::max(1, ncu) * per_cu;
+        ng = std::min(ng, (ntiles + 7) / 8 * 8);
+        s->ngroups = std::max(8, ng / 8 * 8);
+    }
     if (dim == 3 && (rc = dalloc(&s->z_d, Z.size()))) return rc;
     if (s->material && (rc = dalloc(&s->w_d, w.size()))) return rc;
     if ((rc = upload(s->geo_d, geo)) || (rc = upload(s->fgeo_d, fgeo)) || (rc = upload(s->nbr_d, nbr)) ||
@@ -221,9 +245,11 @@ int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) 
     a.fgeo = s->fgeo_d;
     a.nbr = s->nbr_d;
     a.ops = s->ops_d;
+    a.opsfrag = s->opsfrag_d;
     a.itab = s->itab_d;
     a.Kp = (int)s->Kp;
     a.ntiles = (int)(s->Kp / dgw::kTile);
+    a.ngroups = s->ngroups;
     a.dt = (float)dt;
     a.alpha = (float)s->opts.alpha;
     for (int64_t n = 0; n < nsteps; ++n)
@@ -232,7 +258,7 @@ int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) 
             a.qout = s->q[1 - s->cur];
             a.a = (float)kRkA[st5];
             a.b = (float)kRkB[st5];
-            DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, a, st));
+            DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, st));
             s->cur = 1 - s->cur;
         }
     return DGW_OK;
@@ -247,7 +273,7 @@ int upload_fields(dgw_solver *s, const double *q) {
         for (int64_t e = 0; e < K; ++e) {
             const int64_t k = s->perm[e];
             const double *src = q + ((size_t)f * K + k) * Np;
-            for (int n = 0; n < Np; ++n) h[((size_t)f * Np + n) * Kp + e] = (float)src[n];
+            for (int n = 0; n < Np; ++n) h[dgw::tix(e, f * Np + n, nf * Np)] = (float)src[n];
         }
     DGW_HIP(hipMemcpy(s->q[s->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
     return DGW_OK;
@@ -263,7 +289,7 @@ int download(dgw_solver *s, const float *src_d, double *out) {
         for (int64_t e = 0; e < K; ++e) {
             const int64_t k = s->perm[e];
             double *dst = out + ((size_t)f * K + k) * Np;
-            for (int n = 0; n < Np; ++n) dst[n] = h[((size_t)f * Np + n) * Kp + e];
+            for (int n = 0; n < Np; ++n) dst[n] = h[dgw::tix(e, f * Np + n, nf * Np)];
         }
     return DGW_OK;
 }
@@ -356,6 +382,7 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (opts.cfl <= 0) opts.cfl = 1.0;
     if (!(opts.alpha >= 0.0 && opts.alpha <= 1.0)) return fail(DGW_EINVAL, "alpha must be in [0, 1]");
     if (opts.prec != DGW_FP32) return fail(DGW_EINVAL, "precision variant not available in this build");
+    if (opts.kernel < 0 || opts.kernel > 2) return fail(DGW_EINVAL, "kernel variant must be 0, 1 or 2");
     auto t0 = std::chrono::steady_clock::now();
     dgw_solver *s = new (std::nothrow) dgw_solver();
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
@@ -541,14 +568,16 @@ int dgw_rhs(dgw_solver *s, const double *q, double *rhs) {
     a.fgeo = s->fgeo_d;
     a.nbr = s->nbr_d;
     a.ops = s->ops_d;
+    a.opsfrag = s->opsfrag_d;
     a.itab = s->itab_d;
     a.Kp = (int)s->Kp;
     a.ntiles = (int)(s->Kp / dgw::kTile);
+    a.ngroups = s->ngroups;
     a.a = 0.0f;
     a.b = 0.0f;
     a.dt = 1.0f;
     a.alpha = (float)s->opts.alpha;
-    DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, a, s->stream));
+    DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, s->stream));
     s->cur = 1 - s->cur;
     return download(s, s->res, rhs);
 }

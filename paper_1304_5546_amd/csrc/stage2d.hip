@@ -49,20 +49,19 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int Kp = A.Kp;
     const int e = tile * TE + lane;
 
     for (int i = threadIdx.x; i < 3 * 2 * Nfp; i += 256) stab[i] = A.itab[Nafp + i];
 
     // 1. fields of the tile into LDS; prefetch this wave's residual entries
 #pragma unroll
-    for (int row = w; row < 3 * Np; row += NW) sq[row * TE + lane] = A.qin[(size_t)row * Kp + e];
+    for (int row = w; row < 3 * Np; row += NW) sq[row * TE + lane] = A.qin[tix(e, row, 3 * Np)];
     float rres[3][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
 #pragma unroll
-        for (int f = 0; f < 3; ++f) rres[f][r] = A.res[(size_t)(f * Np + n) * Kp + e];
+        for (int f = 0; f < 3; ++f) rres[f][r] = A.res[tix(e, f * Np + n, 3 * Np)];
     }
     __syncthreads();
 
@@ -74,7 +73,7 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
         const float mHx = sq[(0 * Np + own) * TE + lane];
         const float mHy = sq[(1 * Np + own) * TE + lane];
         const float mEz = sq[(2 * Np + own) * TE + lane];
-        const int rec = A.nbr[face * Kp + e];
+        const int rec = A.nbr[tix(e, face, 3)];
         float pHx, pHy, pEz;
         if (rec < 0) {  // PEC wall: mirror state E+ = -E-, H+ = H-
             pHx = mHx;
@@ -83,22 +82,22 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
         } else {
             const int e2 = rec >> 5, f2 = (rec >> 3) & 3, o = rec & 7;
             const int pn = stab[(f2 * 2 + o) * Nfp + i];
-            pHx = A.qin[(size_t)(0 * Np + pn) * Kp + e2];
-            pHy = A.qin[(size_t)(1 * Np + pn) * Kp + e2];
-            pEz = A.qin[(size_t)(2 * Np + pn) * Kp + e2];
+            pHx = A.qin[tix(e2, 0 * Np + pn, 3 * Np)];
+            pHy = A.qin[tix(e2, 1 * Np + pn, 3 * Np)];
+            pEz = A.qin[tix(e2, 2 * Np + pn, 3 * Np)];
         }
-        const float *fg = A.fgeo + (size_t)face * FG * Kp + e;
-        const float nx = fg[0], ny = fg[(size_t)Kp];
+        const float *fg = A.fgeo + tix(e, face * FG, 3 * FG);  // rows face*FG + q are 64 apart
+        const float nx = fg[0], ny = fg[64];
         const float dHx = mHx - pHx, dHy = mHy - pHy, dEz = mEz - pEz;
         const float dh = nx * dHy - ny * dHx;  // jump of the tangential field
         float cEE, cEh, cHE, cHh;
         if (MAT) {
-            cEE = fg[2 * (size_t)Kp];
-            cEh = fg[3 * (size_t)Kp];
-            cHE = fg[4 * (size_t)Kp];
-            cHh = fg[5 * (size_t)Kp];
+            cEE = fg[2 * 64];
+            cEh = fg[3 * 64];
+            cHE = fg[4 * 64];
+            cHh = fg[5 * 64];
         } else {
-            const float hs = 0.5f * fg[2 * (size_t)Kp];
+            const float hs = 0.5f * fg[2 * 64];
             cEE = A.alpha * hs;
             cEh = hs;
             cHE = hs;
@@ -138,8 +137,9 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
             as[2][r] += cs * v2;
         }
     }
-    const float rx = A.geo[e], ry = A.geo[(size_t)Kp + e];
-    const float sx = A.geo[2 * (size_t)Kp + e], sy = A.geo[3 * (size_t)Kp + e];
+    constexpr int G = MAT ? 6 : 4;
+    const float rx = A.geo[tix(e, 0, G)], ry = A.geo[tix(e, 1, G)];
+    const float sx = A.geo[tix(e, 2, G)], sy = A.geo[tix(e, 3, G)];
     float rhs[3][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
         rhs[2][r] = (rx * ar[1][r] + sx * as[1][r]) - (ry * ar[0][r] + sy * as[0][r]);
     }
     if (MAT) {
-        const float ieps = A.geo[4 * (size_t)Kp + e], imu = A.geo[5 * (size_t)Kp + e];
+        const float ieps = A.geo[tix(e, 4, G)], imu = A.geo[tix(e, 5, G)];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             rhs[0][r] *= imu;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
         if (n < Np) {
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const size_t idx = (size_t)(f * Np + n) * Kp + e;
+                const size_t idx = tix(e, f * Np + n, 3 * Np);
                 const float rr = A.a * rres[f][r] + A.dt * rhs[f][r];
                 A.res[idx] = rr;
                 A.qout[idx] = sq[(f * Np + n) * TE + lane] + A.b * rr;
@@ -198,8 +198,9 @@ static hipError_t launch2d(const StageArgs &a, hipStream_t s) {
 hipError_t launch_stage3d(int N, const StageArgs &args, hipStream_t stream);
 const char *stage3d_kernel_name(int N);
 
-hipError_t launch_stage(int dim, int N, bool material, const StageArgs &a, hipStream_t s) {
+hipError_t launch_stage(int dim, int N, bool material, int variant, const StageArgs &a, hipStream_t s) {
     if (dim == 3) return launch_stage3d(N, a, s);
+    if (variant != kVariantScalarOperand) return launch_stage2d_mfma(N, material, a, s);
 #define DGW_CASE(n)                                                    \
     case n:                                                            \
         return material ? launch2d<n, true>(a, s) : launch2d<n, false>(a, s);
@@ -218,9 +219,10 @@ hipError_t launch_stage(int dim, int N, bool material, const StageArgs &a, hipSt
 #undef DGW_CASE
 }
 
-const char *stage_kernel_name(int dim, int N, bool material) {
+const char *stage_kernel_name(int dim, int N, bool material, int variant) {
     (void)N;
     if (dim == 3) return stage3d_kernel_name(N);
+    if (variant != kVariantScalarOperand) return material ? "stage2d_mfma_kernel<N, true>" : "stage2d_mfma_kernel<N, false>";
     return material ? "stage2d_kernel<N, true>" : "stage2d_kernel<N, false>";
 }
 

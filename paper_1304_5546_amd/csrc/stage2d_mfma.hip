@@ -1,0 +1,399 @@
+// Fused LSRK stage for 2D TM Maxwell, FP32, with the element-local
+// contractions on the matrix cores (v_mfma_f32_16x16x4_f32) of gfx950.
+//
+// The right-hand side of eq. dg-strong-explicit is written as ONE contraction
+// per output field with the fused operator Op = [Dr | Ds | LIFT]
+// (Np x (2 Np + 3 Nfp)): since the geometric factors of an affine element are
+// constants, (r_x Dr + s_x Ds) u = Dr (r_x u) + Ds (s_x u), so
+//   rhs_Hx = Op [-r_y Ez; -s_y Ez; flux_Hx] / mu
+//   rhs_Hy = Op [ r_x Ez;  s_x Ez; flux_Hy] / mu
+//   rhs_Ez = Op [r_x Hy - r_y Hx; s_x Hy - s_y Hx; flux_Ez] / eps
+// (the material factors of the flux are folded into its coefficients).
+//
+// Persistent, warp-specialised kernel.  A work-group of 8 waves walks a
+// contiguous run of 64-element tiles inside its XCD's share of the mesh:
+//   - waves 4..7 (producers) stream tile i+1 into one half of a
+//     double-buffered LDS tile: the fields, the geometric factors, the face
+//     data and the partner traces of every face node (gathered through the
+//     compressed face record: partner element, face, orientation; on the PEC
+//     wall the mirror state E+ = -E-, H+ = H- of the element's own trace);
+//   - waves 0..3 (consumers) compute tile i from the other half: consumer w
+//     owns the MFMA N-tile of elements 16w..16w+15.  It contracts the volume
+//     part of K, evaluates the upwind flux (eq. max2d-numflux with the factor
+//     1/2, [q] = q^- - q^+, exact Riemann flux across eps/mu jumps) of its own
+//     16 elements in place of their partner traces, contracts the flux part of
+//     K (the LIFT columns), and applies res <- a res + dt rhs,
+//     q_out <- q_in + b res.
+// The A fragments of Op stay in LDS for the whole kernel; the B fragments are
+// formed on the fly from the LDS tile (times the lane's geometric factors).
+// One barrier per tile hands the buffers over.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace dgw {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <int N, bool MAT>
+struct Tri {
+    static constexpr int Np = (N + 1) * (N + 2) / 2;
+    static constexpr int Nfp = N + 1;
+    static constexpr int Nafp = 3 * Nfp;
+    static constexpr int Kd = 2 * Np + Nafp;
+    static constexpr int KS = (Kd + 3) / 4;
+    static constexpr int MT = (Np + 15) / 16;
+    static constexpr int KV = (2 * Np) / 4;  // K-steps made only of volume columns
+    static constexpr int G = MAT ? 6 : 4;    // per-element factor rows
+    static constexpr int FG = MAT ? 6 : 3;   // per-face data rows
+    // LDS tile rows (each row = 64 elements, stored as 4 sub-tiles of 16)
+    static constexpr int RQ = 0;                 // fields f*Np + n
+    static constexpr int RG = 3 * Np;            // geometric factors
+    static constexpr int RF = RG + G;            // face data face*FG + q
+    static constexpr int RP = RF + 3 * FG;       // partner traces / flux f*Nafp + j
+    static constexpr int R = RP + 3 * Nafp;
+    // sub-tile stride: an odd number of 16-float rows keeps 64-lane row
+    // accesses free of bank conflicts
+    static constexpr int SUB = R * 16 + ((R & 1) ? 0 : 16);
+    static constexpr int BUF = 4 * SUB;
+    static constexpr int PW = (RP + 3) / 4;      // plain rows per producer wave
+    static constexpr int JW = (Nafp + 3) / 4;    // face nodes per producer wave
+    // index of lattice node (i, j) in the order "for j, for i in 0..N-j"
+    __host__ __device__ static constexpr int lat(int i, int j) { return j * (N + 1) - j * (j - 1) / 2 + i; }
+    // t-th node of face f, faces traversed v0->v1, v1->v2, v2->v0
+    __host__ __device__ static constexpr int face_node(int f, int t) {
+        return f == 0 ? t : (f == 1 ? lat(N - t, t) : lat(0, N - t));
+    }
+};
+
+}  // namespace
+
+template <int N, bool MAT>
+__global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
+    using T = Tri<N, MAT>;
+    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, Kd = T::Kd, KS = T::KS, MT = T::MT, KV = T::KV;
+    constexpr int G = T::G, FG = T::FG, RG = T::RG, RF = T::RF, RP = T::RP, SUB = T::SUB, BUF = T::BUF;
+    constexpr int PW = T::PW, JW = T::JW;
+    __shared__ float sbuf[2 * BUF];
+    __shared__ float sa[MT * KS * 64];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool producer = wv >= 4;
+    const int w = wv & 3;
+    const int g = lane >> 4, c = lane & 15;
+
+    for (int i = threadIdx.x; i < MT * KS * 64; i += 512) sa[i] = A.opsfrag[i];
+
+    // tiles of this XCD: a contiguous range, dealt round-robin to its groups
+    const int x = blockIdx.x & 7, bi = blockIdx.x >> 3, GB = gridDim.x >> 3;
+    const int q8 = A.ntiles >> 3, r8 = A.ntiles & 7;
+    const int xbase = x * q8 + (x < r8 ? x : r8), xcount = q8 + (x < r8 ? 1 : 0);
+    if (bi >= xcount) return;  // whole group exits: no tile for it
+
+    // producer state: face records of the next tile to load
+    const int prow = (lane >> 4) * SUB + (lane & 15);  // LDS base of element `lane`
+    int rec_next[3] = {-1, -1, -1};
+    auto load_recs = [&](int tile) {
+        const int e = tile * 64 + lane;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) rec_next[f] = A.nbr[tix(e, f, 3)];
+    };
+    // stream tile `tile` into buffer `b` (producer waves only)
+    auto produce = [&](int tile, int b) {
+        const int e = tile * 64 + lane;
+        int rec[3] = {rec_next[0], rec_next[1], rec_next[2]};
+        float pl[PW];
+#pragma unroll
+        for (int i = 0; i < PW; ++i) {
+            const int r = w + 4 * i;
+            float v = 0.f;
+            if (r < RG)
+                v = A.qin[tix(e, r, 3 * Np)];
+            else if (r < RF)
+                v = A.geo[tix(e, r - RG, G)];
+            else if (r < RP)
+                v = A.fgeo[tix(e, r - RF, 3 * FG)];
+            pl[i] = v;
+        }
+        float pt[JW][3];
+#pragma unroll
+        for (int i = 0; i < JW; ++i) {
+            const int j = w + 4 * i;
+            pt[i][0] = pt[i][1] = pt[i][2] = 0.f;
+            if (j < Nafp) {
+                const int face = j / Nfp, t = j - face * Nfp;
+                const int rc = rec[face];
+                const bool wall = rc < 0;
+                const int e2 = wall ? e : (rc >> 5);
+                const int pn = wall ? T::face_node(face, t) : T::face_node((rc >> 3) & 3, (rc & 7) ? N - t : t);
+#pragma unroll
+                for (int f = 0; f < 3; ++f) pt[i][f] = A.qin[tix(e2, f * Np + pn, 3 * Np)];
+                if (wall) pt[i][2] = -pt[i][2];  // PEC mirror: Ez+ = -Ez-, H+ = H-
+            }
+        }
+        float *B = sbuf + b * BUF + prow;
+#pragma unroll
+        for (int i = 0; i < PW; ++i) {
+            const int r = w + 4 * i;
+            if (r < RP) B[r * 16] = pl[i];
+        }
+#pragma unroll
+        for (int i = 0; i < JW; ++i) {
+            const int j = w + 4 * i;
+            if (j < Nafp) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) B[(RP + f * Nafp + j) * 16] = pt[i][f];
+            }
+        }
+    };
+
+    if (producer) {
+        load_recs(xbase + bi);
+        produce(xbase + bi, 0);
+        if (bi + GB < xcount) load_recs(xbase + bi + GB);
+    }
+    __syncthreads();
+
+    int it = 0;
+    for (int tl = bi; tl < xcount; tl += GB, ++it) {
+        const int cur = it & 1;
+        if (producer) {
+            const int tn = tl + GB;
+            if (tn < xcount) {
+                produce(xbase + tn, cur ^ 1);
+                if (tn + GB < xcount) load_recs(xbase + tn + GB);
+            }
+        } else {
+            const int tile = xbase + tl;
+            const int col = 16 * w + c;
+            const int e_m = tile * 64 + col;
+            const float *B = sbuf + cur * BUF + w * SUB + c;  // this wave's sub-tile, column c
+            float *Bw = sbuf + cur * BUF + w * SUB + c;
+
+            float rr[3][MT][4];
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int n = 16 * mt + 4 * g + jj;
+                        rr[f][mt][jj] = n < Np ? A.res[tix(e_m, f * Np + n, 3 * Np)] : 0.f;
+                    }
+
+            const float rx = B[(RG + 0) * 16], ry = B[(RG + 1) * 16];
+            const float sx = B[(RG + 2) * 16], sy = B[(RG + 3) * 16];
+            float ieps = 1.f, imu = 1.f;
+            if (MAT) {
+                ieps = B[(RG + 4 % G) * 16];
+                imu = B[(RG + 5 % G) * 16];
+            }
+            const float rxH = rx * imu, ryH = ry * imu, sxH = sx * imu, syH = sy * imu;
+            const float rxE = rx * ieps, ryE = ry * ieps, sxE = sx * ieps, syE = sy * ieps;
+
+            // volume part of K
+            floatx4 acc[3][MT];
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[f][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KV; ++ks) {
+                const int k = 4 * ks + g;
+                const bool isr = 4 * ks + 3 < Np ? true : (4 * ks >= Np ? false : k < Np);
+                const int node = isr ? k : k - Np;
+                const float hx = B[(0 * Np + node) * 16];
+                const float hy = B[(1 * Np + node) * 16];
+                const float ez = B[(2 * Np + node) * 16];
+                const float uH = isr ? rxH : sxH, vH = isr ? ryH : syH;
+                const float uE = isr ? rxE : sxE, vE = isr ? ryE : syE;
+                const float b0 = -vH * ez, b1 = uH * ez, b2 = uE * hy - vE * hx;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const float a = sa[(mt * KS + ks) * 64 + lane];
+                    acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][mt], 0, 0, 0);
+                    acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][mt], 0, 0, 0);
+                    acc[2][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, acc[2][mt], 0, 0, 0);
+                }
+                // keep the operand reads of later K-steps from being hoisted
+                // into long-lived registers
+                if (ks % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            }
+
+            // upwind flux of this wave's 16 elements (lane group g takes face
+            // nodes j = g, g+4, ...), written over the partner traces
+#pragma unroll
+            for (int jb = 0; jb < (Nafp + 3) / 4; ++jb) {
+                const int j = 4 * jb + g;
+                if (j < Nafp) {
+                    const int face = j / Nfp, t = j - face * Nfp;
+                    const int own = T::face_node(face, t);
+                    const float mHx = B[(0 * Np + own) * 16];
+                    const float mHy = B[(1 * Np + own) * 16];
+                    const float mEz = B[(2 * Np + own) * 16];
+                    const float pHx = B[(RP + 0 * Nafp + j) * 16];
+                    const float pHy = B[(RP + 1 * Nafp + j) * 16];
+                    const float pEz = B[(RP + 2 * Nafp + j) * 16];
+                    const float *fg = B + (RF + face * FG) * 16;
+                    const float nx = fg[0], ny = fg[16];
+                    const float dHx = mHx - pHx, dHy = mHy - pHy, dEz = mEz - pEz;
+                    const float dh = nx * dHy - ny * dHx;
+                    float cEE, cEh, cHE, cHh;
+                    if (MAT) {
+                        cEE = fg[2 * 16];
+                        cEh = fg[(3 % FG) * 16];
+                        cHE = fg[(4 % FG) * 16];
+                        cHh = fg[(5 % FG) * 16];
+                    } else {
+                        const float hs = 0.5f * fg[2 * 16];
+                        cEE = A.alpha * hs;
+                        cEh = hs;
+                        cHE = hs;
+                        cHh = A.alpha * hs;
+                    }
+                    const float fE = -(cEE * dEz + cEh * dh);
+                    const float fH = cHE * dEz + cHh * dh;
+                    Bw[(RP + 0 * Nafp + j) * 16] = ny * fH;
+                    Bw[(RP + 1 * Nafp + j) * 16] = -nx * fH;
+                    Bw[(RP + 2 * Nafp + j) * 16] = fE;
+                }
+            }
+
+            // flux part of K (including a K-step that straddles the boundary)
+#pragma unroll
+            for (int ks = KV; ks < KS; ++ks) {
+                const int k = 4 * ks + g;
+                const bool vol = k < 2 * Np;
+                const bool ok = k < Kd;
+                const int node = vol ? k - Np : 0;
+                const int jc = (!vol && ok) ? k - 2 * Np : 0;
+                float b0 = ok ? B[(RP + 0 * Nafp + jc) * 16] : 0.f;
+                float b1 = ok ? B[(RP + 1 * Nafp + jc) * 16] : 0.f;
+                float b2 = ok ? B[(RP + 2 * Nafp + jc) * 16] : 0.f;
+                if (4 * ks < 2 * Np) {  // straddling step: s-part rows for k < 2 Np
+                    const float hx = B[(0 * Np + node) * 16];
+                    const float hy = B[(1 * Np + node) * 16];
+                    const float ez = B[(2 * Np + node) * 16];
+                    b0 = vol ? -syH * ez : b0;
+                    b1 = vol ? sxH * ez : b1;
+                    b2 = vol ? sxE * hy - syE * hx : b2;
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const float a = sa[(mt * KS + ks) * 64 + lane];
+                    acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][mt], 0, 0, 0);
+                    acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][mt], 0, 0, 0);
+                    acc[2][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, acc[2][mt], 0, 0, 0);
+                }
+                // keep the operand reads of later K-steps from being hoisted
+                // into long-lived registers
+                if (ks % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            }
+
+            // fused low-storage RK update (lane holds rows 16mt+4g+jj of column col)
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int n = 16 * mt + 4 * g + jj;
+                        if (n < Np) {
+                            const size_t idx = tix(e_m, f * Np + n, 3 * Np);
+                            const float r = A.a * rr[f][mt][jj] + A.dt * acc[f][mt][jj];
+                            A.res[idx] = r;
+                            A.qout[idx] = B[(f * Np + n) * 16] + A.b * r;
+                        }
+                    }
+        }
+        __syncthreads();
+    }
+}
+
+template <int N, bool MAT>
+static hipError_t launch2d_mfma(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((stage2d_mfma_kernel<N, MAT>), dim3(a.ngroups), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N, bool MAT>
+static int occupancy2d_mfma() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_mfma_kernel<N, MAT>, 512, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_stage2d_mfma(int N, bool material, const StageArgs &a, hipStream_t s) {
+#define DGW_CASE(n) \
+    case n:         \
+        return material ? launch2d_mfma<n, true>(a, s) : launch2d_mfma<n, false>(a, s);
+    switch (N) {
+        DGW_CASE(1)
+        DGW_CASE(2)
+        DGW_CASE(3)
+        DGW_CASE(4)
+        DGW_CASE(5)
+        DGW_CASE(6)
+        DGW_CASE(7)
+        DGW_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef DGW_CASE
+}
+
+int blocks_per_cu_2d_mfma(int N, bool material) {
+#define DGW_CASE(n) \
+    case n:         \
+        return material ? occupancy2d_mfma<n, true>() : occupancy2d_mfma<n, false>();
+    switch (N) {
+        DGW_CASE(1)
+        DGW_CASE(2)
+        DGW_CASE(3)
+        DGW_CASE(4)
+        DGW_CASE(5)
+        DGW_CASE(6)
+        DGW_CASE(7)
+        DGW_CASE(8)
+        default:
+            return 1;
+    }
+#undef DGW_CASE
+}
+
+// Fragment-ordered copy of the fused operator [Dr | Ds | LIFT] for the A
+// operand: out[(mt*KS + ks)*64 + l] = Op[16 mt + l%16][4 ks + l/16] (zero
+// outside Np x Kd).  Returns the number of floats written (MT*KS*64).
+int opsfrag2d(int N, const double *Dr, const double *Ds, const double *LIFT, float *out) {
+    const int Np = (N + 1) * (N + 2) / 2, Nafp = 3 * (N + 1), Kd = 2 * Np + Nafp;
+    const int KS = (Kd + 3) / 4, MT = (Np + 15) / 16;
+    if (!out) return MT * KS * 64;
+    for (int mt = 0; mt < MT; ++mt)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const int row = 16 * mt + (l % 16), k = 4 * ks + l / 16;
+                double v = 0.0;
+                if (row < Np && k < Kd) {
+                    if (k < Np)
+                        v = Dr[row * Np + k];
+                    else if (k < 2 * Np)
+                        v = Ds[row * Np + (k - Np)];
+                    else
+                        v = LIFT[row * Nafp + (k - 2 * Np)];
+                }
+                out[(mt * KS + ks) * 64 + l] = (float)v;
+            }
+    return MT * KS * 64;
+}
+
+// The closed-form face node order used by the kernel, for the host's check
+// against the reference element it built.
+int face_node2d(int N, int f, int t) {
+    auto lat = [N](int i, int j) { return j * (N + 1) - j * (j - 1) / 2 + i; };
+    return f == 0 ? t : (f == 1 ? lat(N - t, t) : lat(0, N - t));
+}
+
+}  // namespace dgw

@@ -41,7 +41,7 @@ class Mesh(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("cfl", C.c_double), ("prec", C.c_int32), ("renumber", C.c_int32),
-                ("device", C.c_int32), ("reserved", C.c_int32), ("hip_stream", C.c_void_p)]
+                ("device", C.c_int32), ("kernel", C.c_int32), ("hip_stream", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -144,7 +144,7 @@ class Solver:
     """One DG Maxwell solve (2D TM or 3D) on the GPU behind the C ABI."""
 
     def __init__(self, mesh, order: int, *, alpha: float = 1.0, cfl: float = 1.0, prec="fp32",
-                 renumber: bool = True, device: int = 0, stream=None):
+                 renumber: bool = True, device: int = 0, stream=None, kernel: int = 0):
         L = lib()
         self._keep = []
         vx = np.ascontiguousarray(mesh.vx, dtype=np.float64)
@@ -155,7 +155,7 @@ class Solver:
         mu = None if mesh.mu is None else np.ascontiguousarray(mesh.mu, dtype=np.float64)
         self._keep += [vx, vy, vz, ev, eps, mu]
         m = Mesh(mesh.dim, vx.size, _ptr(vx), _ptr(vy), _ptr(vz), ev.shape[0], _ptr(ev), _ptr(eps), _ptr(mu))
-        o = default_opts(alpha=alpha, cfl=cfl, prec=prec, renumber=int(renumber), device=device)
+        o = default_opts(alpha=alpha, cfl=cfl, prec=prec, renumber=int(renumber), device=device, kernel=kernel)
         if stream is not None:
             o.hip_stream = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         h = C.c_void_p()
