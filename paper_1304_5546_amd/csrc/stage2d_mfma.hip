@@ -96,26 +96,38 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     // producer state: face records of the next tile to load
     const int prow = (lane >> 4) * SUB + (lane & 15);  // LDS base of element `lane`
     int rec_next[3] = {-1, -1, -1};
+    // Addressing: a tile's rows start at a wave-uniform base (kept in scalar
+    // registers), the lane adds a small unsigned 32-bit offset row*64 + lane
+    // (unsigned, so no 64-bit sign extensions are formed and kept live).
     auto load_recs = [&](int tile) {
-        const int e = tile * 64 + lane;
+        const int *nt = A.nbr + (size_t)tile * (3 * 64);
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
 #pragma unroll
-        for (int f = 0; f < 3; ++f) rec_next[f] = A.nbr[tix(e, f, 3)];
+        for (int f = 0; f < 3; ++f) rec_next[f] = nt[(unsigned)(f * 64 + ln)];
     };
     // stream tile `tile` into buffer `b` (producer waves only)
     auto produce = [&](int tile, int b) {
-        const int e = tile * 64 + lane;
+        const float *qt = A.qin + (size_t)tile * (3 * Np * 64);
+        const float *gt = A.geo + (size_t)tile * (G * 64);
+        const float *ft = A.fgeo + (size_t)tile * (3 * FG * 64);
         int rec[3] = {rec_next[0], rec_next[1], rec_next[2]};
+        // lane index opaque to the compiler: keeps the per-row offsets of this
+        // role from being hoisted out of the tile loop, where they would stay
+        // live (and occupy registers) in the other role's code as well
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
         float pl[PW];
 #pragma unroll
         for (int i = 0; i < PW; ++i) {
             const int r = w + 4 * i;
             float v = 0.f;
             if (r < RG)
-                v = A.qin[tix(e, r, 3 * Np)];
+                v = qt[(unsigned)(r * 64 + ln)];
             else if (r < RF)
-                v = A.geo[tix(e, r - RG, G)];
+                v = gt[(unsigned)((r - RG) * 64 + ln)];
             else if (r < RP)
-                v = A.fgeo[tix(e, r - RF, 3 * FG)];
+                v = ft[(unsigned)((r - RF) * 64 + ln)];
             pl[i] = v;
         }
         float pt[JW][3];
@@ -127,10 +139,12 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                 const int face = j / Nfp, t = j - face * Nfp;
                 const int rc = rec[face];
                 const bool wall = rc < 0;
-                const int e2 = wall ? e : (rc >> 5);
+                const int e2 = wall ? tile * 64 + ln : (rc >> 5);
                 const int pn = wall ? T::face_node(face, t) : T::face_node((rc >> 3) & 3, (rc & 7) ? N - t : t);
+                // 32-bit element index of (e2, row pn) in the tiled layout
+                const unsigned i0 = ((unsigned)(e2 >> 6) * (3 * Np) + pn) * 64 + (e2 & 63);
 #pragma unroll
-                for (int f = 0; f < 3; ++f) pt[i][f] = A.qin[tix(e2, f * Np + pn, 3 * Np)];
+                for (int f = 0; f < 3; ++f) pt[i][f] = A.qin[i0 + f * Np * 64];
                 if (wall) pt[i][2] = -pt[i][2];  // PEC mirror: Ez+ = -Ez-, H+ = H-
             }
         }
@@ -168,8 +182,10 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
             }
         } else {
             const int tile = xbase + tl;
-            const int col = 16 * w + c;
-            const int e_m = tile * 64 + col;
+            int col = 16 * w + c;
+            asm volatile("" : "+v"(col));  // see the producer's note
+            float *rt = A.res + (size_t)tile * (3 * Np * 64);
+            float *ot = A.qout + (size_t)tile * (3 * Np * 64);
             const float *B = sbuf + cur * BUF + w * SUB + c;  // this wave's sub-tile, column c
             float *Bw = sbuf + cur * BUF + w * SUB + c;
 
@@ -181,7 +197,7 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int n = 16 * mt + 4 * g + jj;
-                        rr[f][mt][jj] = n < Np ? A.res[tix(e_m, f * Np + n, 3 * Np)] : 0.f;
+                        rr[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
                     }
 
             const float rx = B[(RG + 0) * 16], ry = B[(RG + 1) * 16];
@@ -302,10 +318,10 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                     for (int jj = 0; jj < 4; ++jj) {
                         const int n = 16 * mt + 4 * g + jj;
                         if (n < Np) {
-                            const size_t idx = tix(e_m, f * Np + n, 3 * Np);
+                            const unsigned idx = (unsigned)((f * Np + n) * 64 + col);
                             const float r = A.a * rr[f][mt][jj] + A.dt * acc[f][mt][jj];
-                            A.res[idx] = r;
-                            A.qout[idx] = B[(f * Np + n) * 16] + A.b * r;
+                            rt[idx] = r;
+                            ot[idx] = B[(f * Np + n) * 16] + A.b * r;
                         }
                     }
         }
