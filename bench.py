@@ -37,7 +37,7 @@ CONFIGS = {
 }
 
 
-def cpu_baseline(mesh, N, mode, stages: int = 10):
+def cpu_baseline(mesh, N, mode, stages: int = 5):
     """The FP64 oracle as it stands, on this host's cores, over a bounded
     sample of the same workload: `stages` RK stages on the full mesh."""
     import numpy as np
@@ -71,6 +71,21 @@ def cpu_baseline(mesh, N, mode, stages: int = 10):
                       f"{d.K}-element mesh, {el:.1f} s wall, BLAS threads {threads}"}
 
 
+def recorded_traffic(kernel: str, K: int):
+    """HBM bytes per launch of `kernel` at K elements from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))["kernels"][f"{kernel}@K={K}"]
+        src = open(os.path.join(ROOT, rec["source_file"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_prefix"]:
+        return None
+    return rec["traffic_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +94,9 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel", type=int, default=0, help="stage kernel: 0 auto, 1 scalar-operand VALU, 2 MFMA")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after the timed region, run one plain device copy of this many MiB (a kernel of known "
+                         "traffic, for calibrating HBM byte counters in a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU halo exchange is design-only",
@@ -113,6 +131,7 @@ def main():
     value = dofs * args.steps / (ms * 1e-3)
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
+    kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false>"
     out = {
         "metric": METRIC,
         "value": value,
@@ -131,12 +150,19 @@ def main():
         "accuracy": {"rel_l2_vs_closed_form": err, "t": t_reached},
         "gflops_paper_model": flops_per_launch / launch_s / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": (f"stage2d_kernel<{N}, false>" if args.kernel == 1
-                                else f"stage2d_mfma_kernel<{N}, false>"), "avg_launch_us": launch_s * 1e6,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(kname, solver.K),
+                     "kernel": kname, "avg_launch_us": launch_s * 1e6,
                      "bytes_per_launch": bytes_per_launch},
     }
     solver.close()
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": n * 4, "bytes_written": n * 4}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, N, mode)
     print(json.dumps(out))
