@@ -27,13 +27,16 @@ METRIC = "DOF-updates/s (FP32 vs split-BF16 at stated L2 err); p50/p99 solve lat
 HBM_PEAK_GBS = 8000.0
 
 CONFIGS = {
-    # name: (grid s, mesh seed, permute, order N, mode, description)
+    # name: (grid s, mesh seed, permute, order N, mode, description); "c5" is 3D
     "c1": (8, 1, False, 3, (1, 1), "2D TM PEC cavity, 8x8 grid -> 128 triangles, N=3, mode (1,1)"),
     "c2": (256, 2, True, 5, (2, 3), "2D TM PEC cavity, 256x256 grid -> 131072 randomly permuted triangles "
                                     "(interior vertices jittered +-0.1h), N=5 (Np=21), mode (2,3), "
                                     "5-stage LSRK4 at the CFL step"),
     "c3": (512, 3, False, 7, (2, 3), "2D TM PEC cavity, 512x512 grid -> 524288 triangles, N=7 (Np=36), "
                                      "mode (2,3), 5-stage LSRK4 at the CFL step"),
+    "c5": (48, 5, False, 4, (1, 1, 1), "3D Maxwell PEC cube, 48^3 cubes x 6 -> 663552 tetrahedra (interior "
+                                        "vertices jittered +-0.05h), N=4 (Np=35), mode (1,1,1), 5-stage LSRK4 "
+                                        "at the CFL step"),
 }
 
 
@@ -108,7 +111,11 @@ def main():
     from paper_1304_5546_amd import dgw, inputs
 
     s_grid, seed, permute, N, mode, desc = CONFIGS[args.config]
-    mesh = inputs.tri_grid(s_grid, seed=seed, permute=permute)
+    dim = 3 if len(mode) == 3 else 2
+    if dim == 2:
+        mesh = inputs.tri_grid(s_grid, seed=seed, permute=permute)
+    else:
+        mesh = inputs.tet_grid(s_grid, seed=seed, permute=permute)
     stream = torch.cuda.Stream()
     solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel)
     dt = solver.cfl_dt()
@@ -125,13 +132,16 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     t_reached = (args.warmup + args.steps) * dt
-    err = solver.cavity_error(mode[0], mode[1], 0, t_reached)
+    err = solver.cavity_error(mode[0], mode[1], mode[2] if dim == 3 else 0, t_reached)
 
     dofs = solver.n_fields * solver.K * solver.Np
     value = dofs * args.steps / (ms * 1e-3)
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
-    kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false>"
+    if dim == 3:
+        kname = f"stage3d_kernel<{N}>"
+    else:
+        kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false>"
     out = {
         "metric": METRIC,
         "value": value,
@@ -163,7 +173,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": n * 4, "bytes_written": n * 4}
-    if not args.no_cpu:
+    if not args.no_cpu and dim == 2:
         out["cpu_baseline"] = cpu_baseline(mesh, N, mode)
     print(json.dumps(out))
 

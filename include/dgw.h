@@ -50,7 +50,7 @@ extern "C" {
 #define DGW_OK           0
 #define DGW_EINVAL      -1   /* bad argument (NULL, size, enum)              */
 #define DGW_EMESH       -2   /* J <= 0, non-conforming face, bad vertex id   */
-#define DGW_EORDER      -3   /* order outside 1..8 (2D) / 1..6 (3D)          */
+#define DGW_EORDER      -3   /* order outside 1..8 (2D) / 1..4 (3D solver)   */
 #define DGW_ENOMEM      -4   /* host or device allocation failed             */
 #define DGW_ETOOBIG     -5   /* footprint exceeds a size limit or budget     */
 #define DGW_EDEVICE     -6   /* HIP runtime error (text in dgw_last_error)   */

@@ -62,8 +62,11 @@ hipError_t launch_stage2d_mfma(int N, bool material, const StageArgs &a, hipStre
 // with out == nullptr returns the required length
 int opsfrag2d(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
 int face_node2d(int N, int f, int t);
+// fragment-ordered fused operator [Dr | Ds | Dt | LIFT] of the 3D kernel
+int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, float *out);
 // resident work-groups per CU of the persistent 2D MFMA kernel
 int blocks_per_cu_2d_mfma(int N, bool material);
+int blocks_per_cu_3d(int N);
 
 // FP64 reductions: per-block partial sums of
 //   energy: J_k sum_f w_f q_f^T M q_f     (w from wvec: [n_fields][Kp] FP64 or NULL = 1)

@@ -199,6 +199,9 @@ int setup_device(dgw_solver *s) {
                     return fail(DGW_EINVAL, "internal: face node order mismatch");
         opsfrag.resize(dgw::opsfrag2d(s->N, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag2d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
+    } else {
+        opsfrag.resize(dgw::opsfrag3d(s->N, nullptr, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag3d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.Dt.a.data(), R.LIFT.a.data(), opsfrag.data());
     }
 
     if ((rc = dalloc(&s->geo_d, geo.size())) || (rc = dalloc(&s->fgeo_d, fgeo.size())) ||
@@ -214,7 +217,7 @@ int setup_device(dgw_solver *s) {
     {
         int ncu = 0;
         DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-        const int per_cu = dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material) : 1;
+        const int per_cu = dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material) : dgw::blocks_per_cu_3d(s->N);
         const int ntiles = (int)(Kp / dgw::kTile);
         int ng = std::max(1, ncu) * per_cu;
         ng = std::min(ng, (ntiles + 7) / 8 * 8);
@@ -373,8 +376,8 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (mesh->n_elems <= 0 || mesh->n_verts <= 0) return fail(DGW_EINVAL, "empty mesh");
     if (!mesh->vx || !mesh->vy || (mesh->dim == 3 && !mesh->vz) || !mesh->elem_verts)
         return fail(DGW_EINVAL, "NULL mesh array");
-    if (order < 1 || order > (mesh->dim == 2 ? 8 : 6))
-        return fail(DGW_EORDER, "order must be in 1..8 (2D) or 1..6 (3D)");
+    if (order < 1 || order > (mesh->dim == 2 ? 8 : 4))
+        return fail(DGW_EORDER, "order must be in 1..8 (2D) or 1..4 (3D)");
     if (mesh->n_elems >= (int64_t(1) << 26)) return fail(DGW_ETOOBIG, "more than 2^26 elements");
     dgw_opts opts;
     dgw_opts_default(&opts);
