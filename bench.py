@@ -6,9 +6,10 @@ kernel per stage) over the 2D TM PEC cavity: 256x256 grid -> 131072
 randomly permuted, jittered triangles, order N=5 (Np=21), mode (2,3), CFL
 time step.  Inputs are resident in HBM before the timed region.
 
-    python bench.py [--steps K] [--warmup W] [--config c2|c3|c1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--config c2|c3|c1|c5] [--prec P] [--no-cpu]
 
-Prints one JSON line (metric, value, roofline, cpu_baseline, accuracy).
+Prints one JSON line (metric, value, roofline, cpu_baseline, accuracy, and
+per precision variant the throughput and the relative L2 error at t = 1).
 """
 
 from __future__ import annotations
@@ -89,6 +90,68 @@ def recorded_traffic(kernel: str, K: int):
     return rec["traffic_bytes"]
 
 
+def serve_run(n_requests: int, seed: int = 4, mode: str = "burst", rate: float = 0.0, sequential: bool = False,
+              max_chunk_steps: int = 0):
+    """Run the serving mix (2D TM cavities: s ~ U{16..256}, N in {3,5,7},
+    modes in 1..4, eps = 2.25 in a random disk, t_final ~ U[0.5, 2]) through
+    the request server, or one request at a time through the plain FP32
+    solver (sequential=True).  Returns latency percentiles and aggregate
+    DOF-updates/s over the makespan."""
+    import threading
+
+    import numpy as np
+
+    from paper_1304_5546_amd import dgw, inputs
+
+    reqs = inputs.make_requests(n_requests, seed=seed)
+    meshes = [inputs.request_mesh(r) for r in reqs]
+    np_of = {3: 10, 5: 21, 7: 36}
+    if sequential:
+        t0 = time.perf_counter()
+        dof = 0.0
+        lat = []
+        for r, m in zip(reqs, meshes):
+            a = time.perf_counter()
+            with dgw.Solver(m, r.order) as s:
+                s.set_cavity_mode(*r.mode)
+                n = s.advance(r.t_final)
+                s.energy()
+            dof += 3.0 * m.K * np_of[r.order] * n
+            lat.append(time.perf_counter() - a)
+        span = time.perf_counter() - t0
+        return {"mode": "sequential plain FP32 solver", "requests": n_requests, "makespan_s": span,
+                "dof_updates_per_s": dof / span, "p50_solve_s": float(np.percentile(lat, 50)),
+                "p99_solve_s": float(np.percentile(lat, 99))}
+    arrivals = np.zeros(n_requests) if mode == "burst" else inputs.poisson_arrivals(n_requests, rate, seed + 1000)
+    results = {}
+    with dgw.Server(max_chunk_steps=max_chunk_steps) as srv:
+        tickets = [None] * n_requests
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (r, m) in enumerate(zip(reqs, meshes)):
+                wait = arrivals[i] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                tickets[i] = srv.submit(m, r.order, mode=r.mode, t_final=r.t_final)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for i, t in enumerate(tickets):
+            results[i] = srv.wait(t)[0]
+        span = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array([results[i]["t_finish"] - results[i]["t_arrival"] for i in range(n_requests)])
+    queue = np.array([results[i]["t_start"] - results[i]["t_arrival"] for i in range(n_requests)])
+    ok = sum(1 for i in results if results[i]["status"] == "DGW_OK")
+    return {"mode": f"server, {mode} arrivals" + (f" at {rate:.3g} req/s" if mode != "burst" else ""),
+            "requests": n_requests, "completed_ok": ok, "makespan_s": span,
+            "dof_updates_per_s": st["dof_updates"] / span,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "p50_queue_s": float(np.percentile(queue, 50)), "busy_s": st["busy_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +160,12 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel", type=int, default=0, help="stage kernel: 0 auto, 1 scalar-operand VALU, 2 MFMA")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "split_bf16", "split_fp16"],
+                    help="arithmetic of the timed path (value and roofline)")
+    ap.add_argument("--serve", action="store_true", help="run the serving configuration instead")
+    ap.add_argument("--serve-n", type=int, default=256, help="requests in the serving run")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the other precision variants and their t=1 accuracy runs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB (a kernel of known "
                          "traffic, for calibrating HBM byte counters in a profiler run)")
@@ -105,6 +174,25 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU halo exchange is design-only",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.serve:
+        # the serving configuration: burst (closed-loop capacity), then Poisson
+        # arrivals at 0.8 x that capacity, then the same requests one at a
+        # time through the plain FP32 solver
+        burst = serve_run(args.serve_n)
+        cap = burst["requests"] / burst["makespan_s"]
+        pois = serve_run(args.serve_n, mode="poisson", rate=0.8 * cap)
+        seq = serve_run(args.serve_n, sequential=True)
+        out = {"metric": METRIC, "value": pois["dof_updates_per_s"], "unit": "DOF-updates/s", "n_gpus": 1,
+               "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": f"serving: {args.serve_n} 2D TM cavity requests, s ~ U{{16..256}}, "
+                                      "N in {3,5,7}, eps in {1, 2.25} by random disk, t_final ~ U[0.5, 2]",
+                          "seed": 4},
+               "p50_latency_s": pois["p50_latency_s"], "p99_latency_s": pois["p99_latency_s"],
+               "serving": {"poisson": pois, "burst": burst, "sequential_fp32": seq,
+                           "speedup_vs_sequential": pois["dof_updates_per_s"] / seq["dof_updates_per_s"]}}
+        print(json.dumps(out))
+        return
 
     import torch
 
@@ -117,29 +205,44 @@ def main():
     else:
         mesh = inputs.tet_grid(s_grid, seed=seed, permute=permute)
     stream = torch.cuda.Stream()
-    solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel)
-    dt = solver.cfl_dt()
-    solver.set_cavity_mode(*mode)
+    mode3 = (mode[0], mode[1], mode[2] if dim == 3 else 0)
+
+    def timed(prec):
+        """Warm up, then time exactly args.steps steps on the solver's stream
+        with HIP events; the fields start from the device-initialised mode."""
+        solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec)
+        dt = solver.cfl_dt()
+        solver.set_cavity_mode(*mode)
+        solver.launch_steps(args.warmup, dt, stream)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        solver.launch_steps(args.steps, dt, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        t_reached = (args.warmup + args.steps) * dt
+        err = solver.cavity_error(*mode3, t_reached)
+        return solver, dt, ms, t_reached, err
+
+    def err_at_t1(prec):
+        with dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec) as s1:
+            s1.set_cavity_mode(*mode)
+            n = s1.advance(1.0)
+            return s1.cavity_error(*mode3, 1.0), n
+
+    solver, dt, ms, t_reached, err = timed(args.prec)
     bytes_per_launch, flops_per_launch = solver.stage_cost()
-
-    solver.launch_steps(args.warmup, dt, stream)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    solver.launch_steps(args.steps, dt, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    t_reached = (args.warmup + args.steps) * dt
-    err = solver.cavity_error(mode[0], mode[1], mode[2] if dim == 3 else 0, t_reached)
-
     dofs = solver.n_fields * solver.K * solver.Np
     value = dofs * args.steps / (ms * 1e-3)
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
+    pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2}[args.prec]
     if dim == 3:
         kname = f"stage3d_kernel<{N}>"
+    elif pcode:
+        kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
         kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false>"
     out = {
@@ -153,10 +256,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if pcode == 0 else ("bf16x2+f32acc" if pcode == 1 else "f16x2+f32acc"),
         "data": "synthetic",
         "config": {"workload": desc, "K": solver.K, "N": N, "Np": solver.Np, "dofs": dofs, "dt": dt,
-                   "t_reached": t_reached, "precision": "fp32"},
+                   "t_reached": t_reached, "precision": args.prec},
         "accuracy": {"rel_l2_vs_closed_form": err, "t": t_reached},
         "gflops_paper_model": flops_per_launch / launch_s / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -165,6 +268,20 @@ def main():
                      "bytes_per_launch": bytes_per_launch},
     }
     solver.close()
+    if not args.no_variants and dim == 2:
+        # the same timed run for every precision variant, each with its
+        # relative L2 error against the closed-form mode at t = 1
+        var = {}
+        for prec in ("fp32", "split_bf16", "split_fp16"):
+            if prec == args.prec:
+                v_ms, v_err = ms, err
+            else:
+                sv, _, v_ms, _, v_err = timed(prec)
+                sv.close()
+            e1, n1 = err_at_t1(prec)
+            var[prec] = {"value": dofs * args.steps / (v_ms * 1e-3), "ms_per_step": v_ms / args.steps,
+                         "rel_l2_vs_closed_form_t1": e1, "steps_to_t1": n1}
+        out["variants"] = var
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

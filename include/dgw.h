@@ -81,6 +81,13 @@ typedef struct {
     const double *eps, *mu;
 } dgw_mesh;
 
+/* Arithmetic of the stage contractions.  Fields are FP32 in every variant.
+ * The split variants evaluate each Op*B product (Op = [Dr | Ds | LIFT]) as
+ * Op_hi*B_hi + Op_hi*B_lo + Op_lo*B_hi in 16-bit parts with FP32
+ * accumulation on the matrix cores, and keep the geometric factors, normals
+ * and surface Jacobians in FP64 on the device; 2D only (dgw_create returns
+ * DGW_EINVAL for a 3D mesh, or with kernel = 1).  Measured accuracy is
+ * stated beside every result (relative L2 against the FP64 reference). */
 typedef enum {
     DGW_FP32 = 0,        /* all contractions in FP32                              */
     DGW_SPLIT_BF16 = 1,  /* Dr/Ds/LIFT as BF16 hi+lo split products, FP32 accum.  */
@@ -183,6 +190,83 @@ int dgw_launch_steps(dgw_solver *s, int64_t nsteps, double dt, void *stream);
 /* Kernel name and per-launch algorithmic HBM bytes and flops of one fused
  * stage (the units behind the roofline figures). */
 int dgw_stage_cost(const dgw_solver *s, double *bytes, double *flops);
+
+/* Device bytes dgw_create would allocate for this mesh, order and options
+ * (fields, factors, tables, node coordinates); the request server admits by
+ * this figure.  Host-only, no device call.  Errors: EINVAL, EORDER. */
+int dgw_footprint(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts, int64_t *bytes);
+
+/* ------------------------------------------------------------------ request server */
+/* Continuous batching of many independent cavity solves on one device.
+ * Requests are admitted in arrival order while a slot is free and their
+ * footprint fits the HBM budget; admitted requests are set up on host worker
+ * threads (FP64 geometry, upload, field initialisation) while the device
+ * keeps stepping the running ones.  All running requests of one order and
+ * material class advance together: one batched launch per stage covers the
+ * tiles of every such request (each with its own dt), launches of different
+ * classes run on their own streams and overlap.  Steps are issued in chunks
+ * that end where the next request finishes (or after max_chunk_steps), at
+ * which point finished requests leave, their memory is released and newly
+ * set-up requests join.  Per-element arithmetic does not depend on what else
+ * runs, so a request's result is bitwise the same alone and in any mix.
+ * The server calls are thread-safe; handles are library-owned. */
+typedef struct dgw_server dgw_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;  /* admission limit on summed footprints (<= 0: 80% of free device memory) */
+    int32_t max_slots;         /* maximum admitted requests (<= 0: 64)                                 */
+    int32_t device;            /* HIP device ordinal                                                    */
+    int32_t setup_threads;     /* host set-up / finalisation workers (<= 0: 4)                         */
+    int32_t max_chunk_steps;   /* steps between admission points (<= 0: 64)                             */
+} dgw_server_opts;
+
+/* One solve: the mesh arrays (and q0) are copied by dgw_submit. */
+typedef struct {
+    dgw_mesh mesh;        /* 2D meshes; eps/mu per element or NULL                          */
+    int32_t order;        /* 1..8                                                            */
+    int32_t mode[3];      /* initial fields: the closed-form cavity mode (m, n) at t = 0    */
+    const double *q0;     /* or explicit initial fields [3][K][Np] (caller order); NULL: mode */
+    double t_final;       /* > 0; reached with ceil(t_final / dt_cfl) equal steps              */
+    double alpha;         /* flux parameter in [0, 1]                                          */
+    int32_t prec;         /* DGW_FP32                                                          */
+    int32_t keep_fields;  /* 1: keep the final fields for dgw_wait                             */
+} dgw_request;
+
+typedef struct {
+    int32_t status;        /* DGW_OK, DGW_ECANCELLED, or the error of a failed set-up          */
+    int32_t order;
+    int64_t K;
+    int64_t steps;
+    double dt;
+    double energy;         /* FP64 device reduction of the final fields                         */
+    double rel_l2_mode;    /* relative L2 vs the closed-form mode at t_final when the request
+                              started from a mode with uniform eps, mu; else NaN                 */
+    int64_t footprint_bytes;
+    double t_arrival, t_admit, t_start, t_finish;  /* seconds since dgw_server_create          */
+} dgw_result;
+
+/* Errors: EINVAL, EDEVICE, ENOMEM. */
+int dgw_server_create(const dgw_server_opts *opts, dgw_server **out);
+/* Queue a request; non-blocking.  Errors: EINVAL, EORDER, ETOOBIG (footprint
+ * above the budget: could never be admitted), ECANCELLED (server closing). */
+int dgw_submit(dgw_server *srv, const dgw_request *req, uint64_t *ticket);
+/* *done = 1 once the request has finished, failed or been cancelled.
+ * Errors: ENOTFOUND (unknown or already collected ticket). */
+int dgw_poll(dgw_server *srv, uint64_t ticket, int32_t *done);
+/* Block until the request ends; fill *res (nullable) and, if q_out is not
+ * NULL, the final fields [3][K][Np] in caller order (needs keep_fields).
+ * Collects the ticket.  Returns the request's status (DGW_OK,
+ * DGW_ECANCELLED, ...) or ENOTFOUND / EINVAL. */
+int dgw_wait(dgw_server *srv, uint64_t ticket, double *q_out, dgw_result *res);
+/* Cancel a request that has not finished; a running request leaves at the
+ * next chunk boundary.  Errors: ENOTFOUND. */
+int dgw_cancel(dgw_server *srv, uint64_t ticket);
+/* Server-wide counters: requests completed, DOF-updates issued and the
+ * device-busy seconds they took (summed chunk times). */
+int dgw_server_stats(dgw_server *srv, int64_t *completed, double *dof_updates, double *busy_s);
+/* Cancel everything not finished, wait for the workers, free the device
+ * memory.  Uncollected results are discarded. */
+void dgw_server_destroy(dgw_server *srv);
 
 #ifdef __cplusplus
 }

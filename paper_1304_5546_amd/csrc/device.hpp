@@ -34,6 +34,20 @@ __host__ __device__ inline size_t tix(int64_t e, int row, int rows) {
     return ((size_t)(e >> 6) * rows + row) * 64 + (size_t)(e & 63);
 }
 
+// One solve inside a batched stage launch: its buffers, its first tile in
+// the launch's global tile numbering, and its time step.
+struct BatchDesc {
+    float *q[2];          // ping-pong field buffers
+    float *res;
+    const float *geo;
+    const float *fgeo;
+    const int *nbr;
+    int tile0;            // first global tile of this solve
+    int cur0;             // q[cur0 ^ parity] is the stage input
+    float dt;
+    float pad_;
+};
+
 struct StageArgs {
     const float *qin;
     float *qout;
@@ -44,6 +58,11 @@ struct StageArgs {
     const float *ops;
     const float *opsfrag;  // fused operator in MFMA A-fragment order (2D MFMA kernel)
     const int *itab;
+    const double *geo64;   // FP64 copies of geo / fgeo (split-precision kernels)
+    const double *fgeo64;
+    const BatchDesc *batch;  // batched launches: per-solve descriptors
+    const int *tile_req;     // batched launches: solve index of every tile
+    int parity;              // batched launches: stage count since cur0, mod 2
     int Kp;
     int ntiles;
     int ngroups;  // work-groups of a persistent launch (multiple of 8)
@@ -58,6 +77,10 @@ hipError_t launch_stage(int dim, int N, bool material, int variant, const StageA
 const char *stage_kernel_name(int dim, int N, bool material, int variant);
 
 hipError_t launch_stage2d_mfma(int N, bool material, const StageArgs &a, hipStream_t s);
+// One stage over several solves of the same order and material class at once
+// (a.batch / a.tile_req / a.parity, a.ntiles = total tiles; a.dt unused).
+hipError_t launch_stage2d_batch(int N, bool material, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_2d_batch(int N, bool material);
 // fragment-ordered fused operator [Dr | Ds | LIFT] (see stage2d_mfma.hip);
 // with out == nullptr returns the required length
 int opsfrag2d(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
@@ -67,6 +90,14 @@ int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const
 // resident work-groups per CU of the persistent 2D MFMA kernel
 int blocks_per_cu_2d_mfma(int N, bool material);
 int blocks_per_cu_3d(int N);
+
+// Split-precision 2D stage (prec 1 = BF16 hi+lo, 2 = FP16 hi+lo), FP32
+// accumulation, FP64 geometric factors (geo64 / fgeo64).
+hipError_t launch_stage2d_split(int N, bool material, int prec, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_2d_split(int N, bool material, int prec);
+// 16-bit hi/lo A fragments of a fused operator given row-major in FP64 as
+// [Np][Kd]; with out == nullptr returns the required size in bytes
+int opsfrag_split(int dim, int N, int prec, const double *ops_fused, int Kd, void *out);
 
 // FP64 reductions: per-block partial sums of
 //   energy: J_k sum_f w_f q_f^T M q_f     (w from wvec: [n_fields][Kp] FP64 or NULL = 1)

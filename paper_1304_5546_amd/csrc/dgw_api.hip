@@ -14,6 +14,18 @@
 #include "../../include/dgw.h"
 #include "device.hpp"
 #include "host.hpp"
+#include "solver.hpp"
+
+namespace dgw {
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+}  // namespace dgw
 
 namespace {
 
@@ -24,16 +36,40 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
-// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
-const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
-                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
-const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
-                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
-                        2277821191437.0 / 14882151754819.0};
+using dgw::kRkA;
+using dgw::kRkB;
 
 constexpr int kRedBlocks = 512;
 
 }  // namespace
+
+namespace dgw {
+
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+int64_t solver_footprint(int dim, int order, int64_t K, bool material, int prec) {
+    const int64_t Np = dim == 2 ? (order + 1) * (order + 2) / 2 : (order + 1) * (order + 2) * (order + 3) / 6;
+    const int64_t Nfp = dim == 2 ? order + 1 : (order + 1) * (order + 2) / 2;
+    const int64_t Nf = dim + 1, nf = dim == 2 ? 3 : 6;
+    const int64_t G = dim == 2 ? (material ? 6 : 4) : 9, FG = dim == 2 ? (material ? 6 : 3) : 4;
+    const int64_t Kp = (K + kTile - 1) / kTile * kTile;
+    int64_t b = 3 * nf * Np * Kp * 4;                    // q ping-pong and res
+    b += (G + Nf * FG) * Kp * 4 + Nf * Kp * 4;          // factors and face records
+    if (prec != DGW_FP32) b += (G + Nf * FG) * Kp * 8;  // FP64 factors
+    b += Kp * 4 + Kp * 8 + dim * Np * Kp * 8;           // permutation, J, node coordinates
+    if (material) b += nf * Kp * 8;                     // energy weights
+    b += 4 * Np * (dim * Np + Nf * Nfp) * 4 + Np * Np * 8 + 64 * 1024;  // operators, tables, scratch
+    return b;
+}
+
+void steps_for(double t_final, double dt_cfl, int64_t *n, double *dt) {
+    int64_t k = (int64_t)std::ceil(t_final / dt_cfl - 1e-12);
+    if (k < 1) k = 1;
+    *n = t_final == 0 ? 0 : k;
+    *dt = t_final / k;
+}
+
+}  // namespace dgw
 
 #define DGW_HIP(call)                                                                                     \
     do {                                                                                                  \
@@ -41,32 +77,6 @@ constexpr int kRedBlocks = 512;
         if (e_ != hipSuccess) return fail(DGW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-struct dgw_solver {
-    dgw::RefElement ref;
-    dgw::Geometry g;
-    int dim = 2, N = 1, Np = 0, Nfp = 0, Nfaces = 0, nf = 0;
-    int64_t K = 0, Kp = 0;
-    int G = 0, FG = 0;
-    bool material = false;
-    dgw_opts opts{};
-    std::vector<int> perm;   // internal e -> caller k
-    std::vector<int> iperm;  // caller k -> internal e
-    double dt_cfl = 0.0;
-    int ngroups = 8;  // persistent grid size
-    bool on_device = false;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    float *q[2] = {nullptr, nullptr};
-    float *res = nullptr;
-    int cur = 0;
-    float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr, *opsfrag_d = nullptr;
-    int *nbr_d = nullptr, *itab_d = nullptr, *perm_d = nullptr;
-    double *J_d = nullptr, *M_d = nullptr, *w_d = nullptr, *x_d = nullptr, *y_d = nullptr, *z_d = nullptr;
-    double *partial_d = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    dgw_info info{};
-    double t = 0.0;
-};
 
 namespace {
 
@@ -89,7 +99,8 @@ void free_device(dgw_solver *s) {
     if (!s->on_device) return;
     hipSetDevice(s->opts.device);
     void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->opsfrag_d, s->nbr_d, s->itab_d, s->perm_d,
-                    s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d};
+                    s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d,
+                    s->geo64_d, s->fgeo64_d};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (s->ev0) hipEventDestroy(s->ev0);
@@ -122,8 +133,8 @@ int setup_device(dgw_solver *s) {
     DGW_HIP(hipMemset(s->res, 0, nstate * sizeof(float)));
 
     // per-element factors
-    std::vector<float> geo((size_t)s->G * Kp, 0.0f);
-    std::vector<float> fgeo((size_t)Nf * s->FG * Kp, 0.0f);
+    std::vector<double> geo((size_t)s->G * Kp, 0.0);
+    std::vector<double> fgeo((size_t)Nf * s->FG * Kp, 0.0);
     std::vector<int> nbr((size_t)Nf * Kp, -1);
     std::vector<double> J(Kp, 0.0), w(s->material ? (size_t)nf * Kp : 0, 0.0);
     std::vector<double> X((size_t)Np * Kp, 0.0), Y((size_t)Np * Kp, 0.0), Z(dim == 3 ? (size_t)Np * Kp : 0, 0.0);
@@ -131,10 +142,10 @@ int setup_device(dgw_solver *s) {
     for (int64_t e = 0; e < K; ++e) {
         const int64_t k = s->perm[e];
         const double *D = &g.drst[(size_t)k * dim * dim];
-        for (int c = 0; c < dim * dim; ++c) geo[dgw::tix(e, c, s->G)] = (float)D[c];
+        for (int c = 0; c < dim * dim; ++c) geo[dgw::tix(e, c, s->G)] = D[c];
         if (dim == 2 && s->material) {
-            geo[dgw::tix(e, 4, s->G)] = (float)(1.0 / g.eps[k]);
-            geo[dgw::tix(e, 5, s->G)] = (float)(1.0 / g.mu[k]);
+            geo[dgw::tix(e, 4, s->G)] = 1.0 / g.eps[k];
+            geo[dgw::tix(e, 5, s->G)] = 1.0 / g.mu[k];
         }
         J[e] = g.J[k];
         if (s->material) {
@@ -152,8 +163,8 @@ int setup_device(dgw_solver *s) {
             const double *nrm = &g.normal[kf * dim];
             const double Fs = g.sJ[kf] / g.J[k];
             // rows face*FG + q of this element are 64 apart in the tiled layout
-            float *fg = &fgeo[dgw::tix(e, f * s->FG, Nf * s->FG)];
-            for (int c = 0; c < dim; ++c) fg[(size_t)c * 64] = (float)nrm[c];
+            double *fg = &fgeo[dgw::tix(e, f * s->FG, Nf * s->FG)];
+            for (int c = 0; c < dim; ++c) fg[(size_t)c * 64] = nrm[c];
             const int64_t k2 = g.nbr_elem[kf];
             if (dim == 2 && s->material) {
                 // exact upwind (Riemann) flux across the face, blended by
@@ -163,12 +174,12 @@ int setup_device(dgw_solver *s) {
                 const double sZ = Zm + Zp;
                 const double cEE = alpha / sZ, cEh = 0.5 * (1 - alpha) + alpha * Zp / sZ;
                 const double cHE = 0.5 * (1 - alpha) + alpha * Zm / sZ, cHh = alpha * Zm * Zp / sZ;
-                fg[(size_t)2 * 64] = (float)(Fs / g.eps[k] * cEE);
-                fg[(size_t)3 * 64] = (float)(Fs / g.eps[k] * cEh);
-                fg[(size_t)4 * 64] = (float)(Fs / g.mu[k] * cHE);
-                fg[(size_t)5 * 64] = (float)(Fs / g.mu[k] * cHh);
+                fg[(size_t)2 * 64] = Fs / g.eps[k] * cEE;
+                fg[(size_t)3 * 64] = Fs / g.eps[k] * cEh;
+                fg[(size_t)4 * 64] = Fs / g.mu[k] * cHE;
+                fg[(size_t)5 * 64] = Fs / g.mu[k] * cHh;
             } else {
-                fg[(size_t)dim * 64] = (float)Fs;
+                fg[(size_t)dim * 64] = Fs;
             }
             if (k2 >= 0) {
                 const int64_t e2 = s->iperm[k2];
@@ -190,8 +201,27 @@ int setup_device(dgw_solver *s) {
         for (int o = 0; o < R.n_orient; ++o)
             for (int i = 0; i < Nfp; ++i) itab.push_back(R.face_nodes[f2 * Nfp + R.orient_perm[o * Nfp + i]]);
     std::vector<int> permv(s->perm.begin(), s->perm.end());
+    const bool split = s->opts.prec != DGW_FP32;
     std::vector<float> opsfrag;
-    if (dim == 2) {
+    if (split) {
+        // fused [Dr | Ds | LIFT] in FP64, split into 16-bit hi/lo fragments
+        const int Kd = 2 * Np + Nf * Nfp;
+        std::vector<double> F((size_t)Np * Kd);
+        for (int n = 0; n < Np; ++n) {
+            for (int j = 0; j < Np; ++j) {
+                F[(size_t)n * Kd + j] = R.Dr.a[(size_t)n * Np + j];
+                F[(size_t)n * Kd + Np + j] = R.Ds.a[(size_t)n * Np + j];
+            }
+            for (int j = 0; j < Nf * Nfp; ++j) F[(size_t)n * Kd + 2 * Np + j] = R.LIFT.a[(size_t)n * Nf * Nfp + j];
+        }
+        const int bytes = dgw::opsfrag_split(dim, s->N, s->opts.prec, F.data(), Kd, nullptr);
+        opsfrag.resize(bytes / sizeof(float));
+        dgw::opsfrag_split(dim, s->N, s->opts.prec, F.data(), Kd, opsfrag.data());
+        for (int f = 0; f < Nf; ++f)
+            for (int i = 0; i < Nfp; ++i)
+                if (dgw::face_node2d(s->N, f, i) != R.face_nodes[f * Nfp + i])
+                    return fail(DGW_EINVAL, "internal: face node order mismatch");
+    } else if (dim == 2) {
         // the MFMA kernel indexes face nodes in closed form: confirm it matches
         for (int f = 0; f < Nf; ++f)
             for (int i = 0; i < Nfp; ++i)
@@ -217,7 +247,9 @@ int setup_device(dgw_solver *s) {
     {
         int ncu = 0;
         DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-        const int per_cu = dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material) : dgw::blocks_per_cu_3d(s->N);
+        const int per_cu = split    ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
+                           : dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
+                                      : dgw::blocks_per_cu_3d(s->N);
         const int ntiles = (int)(Kp / dgw::kTile);
         int ng = std::max(1, ncu) * per_cu;
         ng = std::min(ng, (ntiles + 7) / 8 * 8);
@@ -225,7 +257,11 @@ int setup_device(dgw_solver *s) {
     }
     if (dim == 3 && (rc = dalloc(&s->z_d, Z.size()))) return rc;
     if (s->material && (rc = dalloc(&s->w_d, w.size()))) return rc;
-    if ((rc = upload(s->geo_d, geo)) || (rc = upload(s->fgeo_d, fgeo)) || (rc = upload(s->nbr_d, nbr)) ||
+    std::vector<float> geo32(geo.begin(), geo.end()), fgeo32(fgeo.begin(), fgeo.end());
+    if (split && ((rc = dalloc(&s->geo64_d, geo.size())) || (rc = dalloc(&s->fgeo64_d, fgeo.size())) ||
+                  (rc = upload(s->geo64_d, geo)) || (rc = upload(s->fgeo64_d, fgeo))))
+        return rc;
+    if ((rc = upload(s->geo_d, geo32)) || (rc = upload(s->fgeo_d, fgeo32)) || (rc = upload(s->nbr_d, nbr)) ||
         (rc = upload(s->ops_d, ops)) || (rc = upload(s->itab_d, itab)) || (rc = upload(s->perm_d, permv)) ||
         (rc = upload(s->J_d, J)) || (rc = upload(s->M_d, R.M.a)) || (rc = upload(s->x_d, X)) ||
         (rc = upload(s->y_d, Y)))
@@ -241,11 +277,13 @@ int need_device(const dgw_solver *s) {
     return DGW_OK;
 }
 
-int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) {
+dgw::StageArgs stage_args(const dgw_solver *s) {
     dgw::StageArgs a{};
     a.res = s->res;
     a.geo = s->geo_d;
     a.fgeo = s->fgeo_d;
+    a.geo64 = s->geo64_d;
+    a.fgeo64 = s->fgeo64_d;
     a.nbr = s->nbr_d;
     a.ops = s->ops_d;
     a.opsfrag = s->opsfrag_d;
@@ -253,15 +291,25 @@ int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) 
     a.Kp = (int)s->Kp;
     a.ntiles = (int)(s->Kp / dgw::kTile);
     a.ngroups = s->ngroups;
-    a.dt = (float)dt;
     a.alpha = (float)s->opts.alpha;
+    return a;
+}
+
+hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t st) {
+    if (s->opts.prec != DGW_FP32) return dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st);
+    return dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, st);
+}
+
+int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) {
+    dgw::StageArgs a = stage_args(s);
+    a.dt = (float)dt;
     for (int64_t n = 0; n < nsteps; ++n)
         for (int st5 = 0; st5 < 5; ++st5) {
             a.qin = s->q[s->cur];
             a.qout = s->q[1 - s->cur];
             a.a = (float)kRkA[st5];
             a.b = (float)kRkB[st5];
-            DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, st));
+            DGW_HIP(launch_one(s, a, st));
             s->cur = 1 - s->cur;
         }
     return DGW_OK;
@@ -384,8 +432,13 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (opts_in) opts = *opts_in;
     if (opts.cfl <= 0) opts.cfl = 1.0;
     if (!(opts.alpha >= 0.0 && opts.alpha <= 1.0)) return fail(DGW_EINVAL, "alpha must be in [0, 1]");
-    if (opts.prec != DGW_FP32) return fail(DGW_EINVAL, "precision variant not available in this build");
+    if (opts.prec != DGW_FP32 && opts.prec != DGW_SPLIT_BF16 && opts.prec != DGW_SPLIT_FP16)
+        return fail(DGW_EINVAL, "unknown precision variant");
+    if (opts.prec != DGW_FP32 && mesh->dim != 2)
+        return fail(DGW_EINVAL, "split-precision variants are implemented for 2D only");
     if (opts.kernel < 0 || opts.kernel > 2) return fail(DGW_EINVAL, "kernel variant must be 0, 1 or 2");
+    if (opts.prec != DGW_FP32 && opts.kernel == 1)
+        return fail(DGW_EINVAL, "split-precision variants run on the matrix cores only (kernel 0 or 2)");
     auto t0 = std::chrono::steady_clock::now();
     dgw_solver *s = new (std::nothrow) dgw_solver();
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
@@ -546,13 +599,11 @@ int dgw_advance(dgw_solver *s, double t_final, double dt, int64_t *steps_taken) 
     if (!(t_final >= 0)) return fail(DGW_EINVAL, "t_final must be >= 0");
     int64_t n;
     if (dt <= 0) {
-        n = (int64_t)std::ceil(t_final / s->dt_cfl - 1e-12);
-        if (n < 1) n = 1;
-        dt = t_final / n;
+        dgw::steps_for(t_final, s->dt_cfl, &n, &dt);
     } else {
         n = (int64_t)std::llround(t_final / dt);
+        if (t_final == 0) n = 0;
     }
-    if (t_final == 0) n = 0;
     if ((rc = dgw_advance_steps(s, n, dt))) return rc;
     if (steps_taken) *steps_taken = n;
     return DGW_OK;
@@ -563,24 +614,13 @@ int dgw_rhs(dgw_solver *s, const double *q, double *rhs) {
     if (rc) return rc;
     if (!q || !rhs) return fail(DGW_EINVAL, "NULL argument");
     if ((rc = dgw_set_fields(s, q))) return rc;
-    dgw::StageArgs a{};
+    dgw::StageArgs a = stage_args(s);
     a.qin = s->q[s->cur];
     a.qout = s->q[1 - s->cur];
-    a.res = s->res;
-    a.geo = s->geo_d;
-    a.fgeo = s->fgeo_d;
-    a.nbr = s->nbr_d;
-    a.ops = s->ops_d;
-    a.opsfrag = s->opsfrag_d;
-    a.itab = s->itab_d;
-    a.Kp = (int)s->Kp;
-    a.ntiles = (int)(s->Kp / dgw::kTile);
-    a.ngroups = s->ngroups;
     a.a = 0.0f;
     a.b = 0.0f;
     a.dt = 1.0f;
-    a.alpha = (float)s->opts.alpha;
-    DGW_HIP(dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, s->stream));
+    DGW_HIP(launch_one(s, a, s->stream));
     s->cur = 1 - s->cur;
     return download(s, s->res, rhs);
 }
@@ -691,9 +731,10 @@ int dgw_stage_cost(const dgw_solver *s, double *bytes, double *flops) {
     if (!s) return fail(DGW_EINVAL, "NULL solver");
     const int Nafp = s->Nfaces * s->Nfp;
     // algorithmic HBM traffic per element: read q_in and res, write res and
-    // q_out (4 words per DOF) plus the per-element and per-face factors and
-    // the face records
-    const double per_el = 16.0 * s->nf * s->Np + 4.0 * s->G + s->Nfaces * (4.0 * s->FG + 4.0);
+    // q_out (4 words per DOF) plus the per-element and per-face factors (FP32,
+    // or FP64 in the split-precision variants) and the face records
+    const double wg = s->opts.prec == DGW_FP32 ? 4.0 : 8.0;
+    const double per_el = 16.0 * s->nf * s->Np + wg * s->G + s->Nfaces * (wg * s->FG + 4.0);
     if (bytes) *bytes = per_el * double(s->K);
     if (flops) *flops = flops_per_element(s->dim, s->Np, Nafp, s->nf) * double(s->K);
     return DGW_OK;

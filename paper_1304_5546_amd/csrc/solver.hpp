@@ -1,0 +1,59 @@
+// Library-internal state of one solve (the opaque dgw_solver of the C ABI),
+// shared by the solver calls and the request server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dgw.h"
+#include "device.hpp"
+#include "host.hpp"
+
+struct dgw_solver {
+    dgw::RefElement ref;
+    dgw::Geometry g;
+    int dim = 2, N = 1, Np = 0, Nfp = 0, Nfaces = 0, nf = 0;
+    int64_t K = 0, Kp = 0;
+    int G = 0, FG = 0;
+    bool material = false;
+    dgw_opts opts{};
+    std::vector<int> perm;   // internal e -> caller k
+    std::vector<int> iperm;  // caller k -> internal e
+    double dt_cfl = 0.0;
+    int ngroups = 8;  // persistent grid size
+    bool on_device = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    float *q[2] = {nullptr, nullptr};
+    float *res = nullptr;
+    int cur = 0;
+    float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr, *opsfrag_d = nullptr;
+    double *geo64_d = nullptr, *fgeo64_d = nullptr;  // split-precision variants only
+    int *nbr_d = nullptr, *itab_d = nullptr, *perm_d = nullptr;
+    double *J_d = nullptr, *M_d = nullptr, *w_d = nullptr, *x_d = nullptr, *y_d = nullptr, *z_d = nullptr;
+    double *partial_d = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    dgw_info info{};
+    double t = 0.0;
+};
+
+namespace dgw {
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+extern const double kRkA[5];
+extern const double kRkB[5];
+
+// Device bytes a solver of this size allocates (fields, factors, tables,
+// coordinates, reduction scratch).
+int64_t solver_footprint(int dim, int order, int64_t K, bool material, int prec);
+
+// Set the calling thread's last-error text; returns code.
+int set_error(int code, const std::string &msg);
+
+// Step count and step for reaching t_final at (at most) the CFL step.
+void steps_for(double t_final, double dt_cfl, int64_t *n, double *dt);
+
+}  // namespace dgw

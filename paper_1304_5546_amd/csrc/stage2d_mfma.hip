@@ -68,9 +68,33 @@ struct Tri {
     }
 };
 
+// Buffers of the solve that owns global tile t, and t's index inside it.
+struct TileSrc {
+    const float *qin;
+    float *qout;
+    float *res;
+    const float *geo, *fgeo;
+    const int *nbr;
+    int tile;
+    float dt;
+};
+
+template <bool BATCH>
+__device__ __forceinline__ TileSrc tile_src(const StageArgs &A, int t) {
+    if constexpr (!BATCH) {
+        return TileSrc{A.qin, A.qout, A.res, A.geo, A.fgeo, A.nbr, t, A.dt};
+    } else {
+        // t is wave-uniform, so these are scalar loads of the descriptor
+        const int r = __builtin_amdgcn_readfirstlane(A.tile_req[t]);
+        const BatchDesc &d = A.batch[r];
+        const int ci = (d.cur0 ^ A.parity) & 1;
+        return TileSrc{d.q[ci], d.q[ci ^ 1], d.res, d.geo, d.fgeo, d.nbr, t - d.tile0, d.dt};
+    }
+}
+
 }  // namespace
 
-template <int N, bool MAT>
+template <int N, bool MAT, bool BATCH>
 __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     using T = Tri<N, MAT>;
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, Kd = T::Kd, KS = T::KS, MT = T::MT, KV = T::KV;
@@ -100,7 +124,8 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     // registers), the lane adds a small unsigned 32-bit offset row*64 + lane
     // (unsigned, so no 64-bit sign extensions are formed and kept live).
     auto load_recs = [&](int tile) {
-        const int *nt = A.nbr + (size_t)tile * (3 * 64);
+        const TileSrc S = tile_src<BATCH>(A, tile);
+        const int *nt = S.nbr + (size_t)S.tile * (3 * 64);
         int ln = lane;
         asm volatile("" : "+v"(ln));
 #pragma unroll
@@ -108,9 +133,10 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     };
     // stream tile `tile` into buffer `b` (producer waves only)
     auto produce = [&](int tile, int b) {
-        const float *qt = A.qin + (size_t)tile * (3 * Np * 64);
-        const float *gt = A.geo + (size_t)tile * (G * 64);
-        const float *ft = A.fgeo + (size_t)tile * (3 * FG * 64);
+        const TileSrc S = tile_src<BATCH>(A, tile);
+        const float *qt = S.qin + (size_t)S.tile * (3 * Np * 64);
+        const float *gt = S.geo + (size_t)S.tile * (G * 64);
+        const float *ft = S.fgeo + (size_t)S.tile * (3 * FG * 64);
         int rec[3] = {rec_next[0], rec_next[1], rec_next[2]};
         // lane index opaque to the compiler: keeps the per-row offsets of this
         // role from being hoisted out of the tile loop, where they would stay
@@ -139,12 +165,12 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                 const int face = j / Nfp, t = j - face * Nfp;
                 const int rc = rec[face];
                 const bool wall = rc < 0;
-                const int e2 = wall ? tile * 64 + ln : (rc >> 5);
+                const int e2 = wall ? S.tile * 64 + ln : (rc >> 5);
                 const int pn = wall ? T::face_node(face, t) : T::face_node((rc >> 3) & 3, (rc & 7) ? N - t : t);
                 // 32-bit element index of (e2, row pn) in the tiled layout
                 const unsigned i0 = ((unsigned)(e2 >> 6) * (3 * Np) + pn) * 64 + (e2 & 63);
 #pragma unroll
-                for (int f = 0; f < 3; ++f) pt[i][f] = A.qin[i0 + f * Np * 64];
+                for (int f = 0; f < 3; ++f) pt[i][f] = S.qin[i0 + f * Np * 64];
                 if (wall) pt[i][2] = -pt[i][2];  // PEC mirror: Ez+ = -Ez-, H+ = H-
             }
         }
@@ -184,8 +210,10 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
             const int tile = xbase + tl;
             int col = 16 * w + c;
             asm volatile("" : "+v"(col));  // see the producer's note
-            float *rt = A.res + (size_t)tile * (3 * Np * 64);
-            float *ot = A.qout + (size_t)tile * (3 * Np * 64);
+            const TileSrc S = tile_src<BATCH>(A, tile);
+            float *rt = S.res + (size_t)S.tile * (3 * Np * 64);
+            float *ot = S.qout + (size_t)S.tile * (3 * Np * 64);
+            const float dt = S.dt;
             const float *B = sbuf + cur * BUF + w * SUB + c;  // this wave's sub-tile, column c
             float *Bw = sbuf + cur * BUF + w * SUB + c;
 
@@ -319,7 +347,7 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                         const int n = 16 * mt + 4 * g + jj;
                         if (n < Np) {
                             const unsigned idx = (unsigned)((f * Np + n) * 64 + col);
-                            const float r = A.a * rr[f][mt][jj] + A.dt * acc[f][mt][jj];
+                            const float r = A.a * rr[f][mt][jj] + dt * acc[f][mt][jj];
                             rt[idx] = r;
                             ot[idx] = B[(f * Np + n) * 16] + A.b * r;
                         }
@@ -329,53 +357,62 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     }
 }
 
-template <int N, bool MAT>
+template <int N, bool MAT, bool BATCH>
 static hipError_t launch2d_mfma(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((stage2d_mfma_kernel<N, MAT>), dim3(a.ngroups), dim3(512), 0, s, a);
+    // every pointer the kernel dereferences must be set
+    if (!a.opsfrag || a.ntiles <= 0 || a.ngroups < 8 || (a.ngroups & 7)) return hipErrorInvalidValue;
+    if (BATCH ? (!a.batch || !a.tile_req) : (!a.qin || !a.qout || !a.res || !a.geo || !a.fgeo || !a.nbr))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((stage2d_mfma_kernel<N, MAT, BATCH>), dim3(a.ngroups), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
-template <int N, bool MAT>
+template <int N, bool MAT, bool BATCH>
 static int occupancy2d_mfma() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_mfma_kernel<N, MAT>, 512, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_mfma_kernel<N, MAT, BATCH>, 512, 0) != hipSuccess)
+        return 1;
     return nb > 0 ? nb : 1;
 }
 
+#define DGW_ORDERS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+
 hipError_t launch_stage2d_mfma(int N, bool material, const StageArgs &a, hipStream_t s) {
 #define DGW_CASE(n) \
-    case n:         \
-        return material ? launch2d_mfma<n, true>(a, s) : launch2d_mfma<n, false>(a, s);
+    case n: return material ? launch2d_mfma<n, true, false>(a, s) : launch2d_mfma<n, false, false>(a, s);
     switch (N) {
-        DGW_CASE(1)
-        DGW_CASE(2)
-        DGW_CASE(3)
-        DGW_CASE(4)
-        DGW_CASE(5)
-        DGW_CASE(6)
-        DGW_CASE(7)
-        DGW_CASE(8)
-        default:
-            return hipErrorInvalidValue;
+        DGW_ORDERS(DGW_CASE)
+        default: return hipErrorInvalidValue;
+    }
+#undef DGW_CASE
+}
+
+hipError_t launch_stage2d_batch(int N, bool material, const StageArgs &a, hipStream_t s) {
+#define DGW_CASE(n) \
+    case n: return material ? launch2d_mfma<n, true, true>(a, s) : launch2d_mfma<n, false, true>(a, s);
+    switch (N) {
+        DGW_ORDERS(DGW_CASE)
+        default: return hipErrorInvalidValue;
     }
 #undef DGW_CASE
 }
 
 int blocks_per_cu_2d_mfma(int N, bool material) {
 #define DGW_CASE(n) \
-    case n:         \
-        return material ? occupancy2d_mfma<n, true>() : occupancy2d_mfma<n, false>();
+    case n: return material ? occupancy2d_mfma<n, true, false>() : occupancy2d_mfma<n, false, false>();
     switch (N) {
-        DGW_CASE(1)
-        DGW_CASE(2)
-        DGW_CASE(3)
-        DGW_CASE(4)
-        DGW_CASE(5)
-        DGW_CASE(6)
-        DGW_CASE(7)
-        DGW_CASE(8)
-        default:
-            return 1;
+        DGW_ORDERS(DGW_CASE)
+        default: return 1;
+    }
+#undef DGW_CASE
+}
+
+int blocks_per_cu_2d_batch(int N, bool material) {
+#define DGW_CASE(n) \
+    case n: return material ? occupancy2d_mfma<n, true, true>() : occupancy2d_mfma<n, false, true>();
+    switch (N) {
+        DGW_ORDERS(DGW_CASE)
+        default: return 1;
     }
 #undef DGW_CASE
 }

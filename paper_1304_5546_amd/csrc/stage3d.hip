@@ -265,6 +265,10 @@ __global__ void __launch_bounds__(256) stage3d_kernel(StageArgs A) {
 
 template <int N>
 static hipError_t launch3d(const StageArgs &a, hipStream_t s) {
+    // every pointer the kernel dereferences must be set
+    if (!a.opsfrag || !a.itab || !a.qin || !a.qout || !a.res || !a.geo || !a.fgeo || !a.nbr || a.ntiles <= 0 ||
+        a.ngroups < 8 || (a.ngroups & 7))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL((stage3d_kernel<N>), dim3(a.ngroups), dim3(256), 0, s, a);
     return hipGetLastError();
 }

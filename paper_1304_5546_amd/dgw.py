@@ -49,6 +49,28 @@ class Info(C.Structure):
                 ("solve_ms", C.c_double), ("dof_updates_per_s", C.c_double)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("device", C.c_int32),
+                ("setup_threads", C.c_int32), ("max_chunk_steps", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("mesh", Mesh), ("order", C.c_int32), ("mode", C.c_int32 * 3), ("q0", C.c_void_p),
+                ("t_final", C.c_double), ("alpha", C.c_double), ("prec", C.c_int32), ("keep_fields", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("order", C.c_int32), ("K", C.c_int64), ("steps", C.c_int64),
+                ("dt", C.c_double), ("energy", C.c_double), ("rel_l2_mode", C.c_double),
+                ("footprint_bytes", C.c_int64), ("t_arrival", C.c_double), ("t_admit", C.c_double),
+                ("t_start", C.c_double), ("t_finish", C.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status"] = ERRORS.get(self.status, self.status)
+        return d
+
+
 _lib = None
 
 
@@ -92,6 +114,14 @@ def lib() -> C.CDLL:
             "dgw_get_fields_dev": (C.c_int, [P, P, P]),
             "dgw_launch_steps": (C.c_int, [P, I64, D, P]),
             "dgw_stage_cost": (C.c_int, [P, P, P]),
+            "dgw_footprint": (C.c_int, [P, I32, P, P]),
+            "dgw_server_create": (C.c_int, [P, P]),
+            "dgw_submit": (C.c_int, [P, P, P]),
+            "dgw_poll": (C.c_int, [P, C.c_uint64, P]),
+            "dgw_wait": (C.c_int, [P, C.c_uint64, P, P]),
+            "dgw_cancel": (C.c_int, [P, C.c_uint64]),
+            "dgw_server_stats": (C.c_int, [P, P, P, P]),
+            "dgw_server_destroy": (None, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -272,3 +302,92 @@ class Solver:
 
     def launch_steps(self, nsteps: int, dt: float, stream=None):
         _check(lib().dgw_launch_steps(self._h, int(nsteps), float(dt), self._stream_ptr(stream)), "dgw_launch_steps")
+
+
+def _mesh_struct(mesh, keep: list) -> Mesh:
+    vx = np.ascontiguousarray(mesh.vx, dtype=np.float64)
+    vy = np.ascontiguousarray(mesh.vy, dtype=np.float64)
+    vz = None if mesh.vz is None else np.ascontiguousarray(mesh.vz, dtype=np.float64)
+    ev = np.ascontiguousarray(mesh.elem_verts, dtype=np.int32)
+    eps = None if mesh.eps is None else np.ascontiguousarray(mesh.eps, dtype=np.float64)
+    mu = None if mesh.mu is None else np.ascontiguousarray(mesh.mu, dtype=np.float64)
+    keep += [vx, vy, vz, ev, eps, mu]
+    return Mesh(mesh.dim, vx.size, _ptr(vx), _ptr(vy), _ptr(vz), ev.shape[0], _ptr(ev), _ptr(eps), _ptr(mu))
+
+
+def footprint(mesh, order: int, prec="fp32") -> int:
+    """Device bytes a solver of this mesh and order allocates."""
+    keep: list = []
+    m = _mesh_struct(mesh, keep)
+    o = default_opts(prec=prec)
+    b = C.c_int64()
+    _check(lib().dgw_footprint(C.byref(m), order, C.byref(o), C.byref(b)), "dgw_footprint")
+    return b.value
+
+
+class Server:
+    """Continuous-batching request server (``dgw_server_*``): submit cavity
+    solves, wait for their results."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 0, device: int = 0, setup_threads: int = 0,
+                 max_chunk_steps: int = 0):
+        o = ServerOpts(hbm_budget_bytes, max_slots, device, setup_threads, max_chunk_steps)
+        h = C.c_void_p()
+        _check(lib().dgw_server_create(C.byref(o), C.byref(h)), "dgw_server_create")
+        self._h = h
+        self._np = {}
+
+    def submit(self, mesh, order: int, *, mode=(1, 1), q0: np.ndarray | None = None, t_final: float = 1.0,
+               alpha: float = 1.0, prec="fp32", keep_fields: bool = False) -> int:
+        keep: list = []
+        m = _mesh_struct(mesh, keep)
+        q = None if q0 is None else np.ascontiguousarray(q0, dtype=np.float64)
+        md = (C.c_int32 * 3)(*(list(mode) + [0] * (3 - len(mode))))
+        r = Request(m, order, md, _ptr(q), t_final, alpha, PRECISIONS[prec] if isinstance(prec, str) else prec,
+                    int(keep_fields))
+        t = C.c_uint64()
+        _check(lib().dgw_submit(self._h, C.byref(r), C.byref(t)), "dgw_submit")
+        self._np[t.value] = (mesh.elem_verts.shape[0], (order + 1) * (order + 2) // 2)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        _check(lib().dgw_poll(self._h, ticket, C.byref(d)), "dgw_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int, fields: bool = False):
+        """Block until the request ends; returns (result dict, fields or None).
+        A cancelled request returns status DGW_ECANCELLED (no exception)."""
+        K, Np = self._np.get(ticket, (0, 0))
+        q = np.zeros((3, K, Np)) if fields else None
+        res = Result()
+        rc = lib().dgw_wait(self._h, ticket, _ptr(q), C.byref(res))
+        if rc not in (0, -8) and res.status == 0:
+            _check(rc, "dgw_wait")
+        self._np.pop(ticket, None)
+        return res.as_dict(), (q if rc == 0 else None)
+
+    def cancel(self, ticket: int):
+        _check(lib().dgw_cancel(self._h, ticket), "dgw_cancel")
+
+    def stats(self) -> dict:
+        n, d, b = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().dgw_server_stats(self._h, C.byref(n), C.byref(d), C.byref(b)), "dgw_server_stats")
+        return {"completed": n.value, "dof_updates": d.value, "busy_s": b.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dgw_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -138,9 +138,28 @@ def test_error_paths_before_any_device_call():
     t = inputs.tet_grid(1)
     t.eps = np.full(t.K, 2.0)
     _expect("DGW_EINVAL", lambda: dgw.Solver(t, 2, device=-1))
+    # split precision: 2D only, matrix-core kernels only, known variants only
+    _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="split_bf16", device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec="split_fp16", kernel=1, device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec=7, device=-1))
     # NULL arguments at the raw ABI
     L = dgw.lib()
     h = C.c_void_p()
     assert L.dgw_create(None, 3, None, C.byref(h)) == -1
     assert L.dgw_reference_element(4, 3, None, None, *([None] * 9)) == -1
     assert L.dgw_reference_element(2, 12, None, None, *([None] * 9)) == -3
+
+
+def test_footprint_is_host_only_and_scales():
+    """dgw_footprint needs no device: state is 3 arrays x 3 fields x Np x Kp
+    FP32 plus factors, tables and FP64 node coordinates."""
+    m = inputs.tri_grid(16, seed=1)
+    f3, f5 = dgw.footprint(m, 3), dgw.footprint(m, 5)
+    assert f5 > f3 > 0
+    Kp = (m.K + 63) // 64 * 64
+    assert f5 >= 3 * 3 * 21 * Kp * 4 + 2 * 21 * Kp * 8
+    mat = inputs.tri_grid(16, seed=1)
+    mat.eps = np.full(mat.K, 2.25)
+    assert dgw.footprint(mat, 5) > f5  # material factors and energy weights
+    assert dgw.footprint(m, 5, prec="split_bf16") > f5  # FP64 factors
+    _expect("DGW_EORDER", lambda: dgw.footprint(m, 9))
