@@ -118,6 +118,8 @@ def serve_run(n_requests: int, seed: int = 4, mode: str = "burst", rate: float =
                 s.energy()
             dof += 3.0 * m.K * np_of[r.order] * n
             lat.append(time.perf_counter() - a)
+            if len(lat) % 32 == 0:
+                print(f"[serve] sequential: {len(lat)}/{n_requests} done", file=sys.stderr, flush=True)
         span = time.perf_counter() - t0
         return {"mode": "sequential plain FP32 solver", "requests": n_requests, "makespan_s": span,
                 "dof_updates_per_s": dof / span, "p50_solve_s": float(np.percentile(lat, 50)),
@@ -140,6 +142,8 @@ def serve_run(n_requests: int, seed: int = 4, mode: str = "burst", rate: float =
         th.join()
         for i, t in enumerate(tickets):
             results[i] = srv.wait(t)[0]
+            if (i + 1) % 32 == 0:
+                print(f"[serve] {mode}: {i + 1}/{n_requests} collected", file=sys.stderr, flush=True)
         span = time.perf_counter() - t0
         st = srv.stats()
     lat = np.array([results[i]["t_finish"] - results[i]["t_arrival"] for i in range(n_requests)])
@@ -240,7 +244,7 @@ def main():
     achieved = bytes_per_launch / launch_s / 1e9
     pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2}[args.prec]
     if dim == 3:
-        kname = f"stage3d_kernel<{N}>"
+        kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
@@ -268,11 +272,11 @@ def main():
                      "bytes_per_launch": bytes_per_launch},
     }
     solver.close()
-    if not args.no_variants and dim == 2:
+    if not args.no_variants:
         # the same timed run for every precision variant, each with its
         # relative L2 error against the closed-form mode at t = 1
         var = {}
-        for prec in ("fp32", "split_bf16", "split_fp16"):
+        for prec in ("fp32", "split_bf16", "split_fp16") if dim == 2 else ("fp32", "split_bf16"):
             if prec == args.prec:
                 v_ms, v_err = ms, err
             else:

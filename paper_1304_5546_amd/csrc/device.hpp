@@ -95,9 +95,13 @@ int blocks_per_cu_3d(int N);
 // accumulation, FP64 geometric factors (geo64 / fgeo64).
 hipError_t launch_stage2d_split(int N, bool material, int prec, const StageArgs &a, hipStream_t s);
 int blocks_per_cu_2d_split(int N, bool material, int prec);
-// 16-bit hi/lo A fragments of a fused operator given row-major in FP64 as
-// [Np][Kd]; with out == nullptr returns the required size in bytes
-int opsfrag_split(int dim, int N, int prec, const double *ops_fused, int Kd, void *out);
+// 16-bit hi/lo operator fragments of the 2D split kernel (Dr, Ds, LIFT given
+// row-major in FP64); with out == nullptr returns the required size in bytes
+int opsfrag2d_split(int N, int prec, const double *Dr, const double *Ds, const double *LIFT, void *out);
+// Split-BF16 3D stage (FP64 geo64 / fgeo64) and its operator fragments
+hipError_t launch_stage3d_split(int N, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_3d_split(int N);
+int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, void *out);
 
 // FP64 reductions: per-block partial sums of
 //   energy: J_k sum_f w_f q_f^T M q_f     (w from wvec: [n_fields][Kp] FP64 or NULL = 1)

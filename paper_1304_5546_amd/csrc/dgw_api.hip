@@ -203,20 +203,14 @@ int setup_device(dgw_solver *s) {
     std::vector<int> permv(s->perm.begin(), s->perm.end());
     const bool split = s->opts.prec != DGW_FP32;
     std::vector<float> opsfrag;
-    if (split) {
-        // fused [Dr | Ds | LIFT] in FP64, split into 16-bit hi/lo fragments
-        const int Kd = 2 * Np + Nf * Nfp;
-        std::vector<double> F((size_t)Np * Kd);
-        for (int n = 0; n < Np; ++n) {
-            for (int j = 0; j < Np; ++j) {
-                F[(size_t)n * Kd + j] = R.Dr.a[(size_t)n * Np + j];
-                F[(size_t)n * Kd + Np + j] = R.Ds.a[(size_t)n * Np + j];
-            }
-            for (int j = 0; j < Nf * Nfp; ++j) F[(size_t)n * Kd + 2 * Np + j] = R.LIFT.a[(size_t)n * Nf * Nfp + j];
-        }
-        const int bytes = dgw::opsfrag_split(dim, s->N, s->opts.prec, F.data(), Kd, nullptr);
+    if (split && dim == 3) {
+        const int bytes = dgw::opsfrag3d_split(s->N, nullptr, nullptr, nullptr, nullptr, nullptr);
         opsfrag.resize(bytes / sizeof(float));
-        dgw::opsfrag_split(dim, s->N, s->opts.prec, F.data(), Kd, opsfrag.data());
+        dgw::opsfrag3d_split(s->N, R.Dr.a.data(), R.Ds.a.data(), R.Dt.a.data(), R.LIFT.a.data(), opsfrag.data());
+    } else if (split) {
+        const int bytes = dgw::opsfrag2d_split(s->N, s->opts.prec, nullptr, nullptr, nullptr, nullptr);
+        opsfrag.resize(bytes / sizeof(float));
+        dgw::opsfrag2d_split(s->N, s->opts.prec, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
         for (int f = 0; f < Nf; ++f)
             for (int i = 0; i < Nfp; ++i)
                 if (dgw::face_node2d(s->N, f, i) != R.face_nodes[f * Nfp + i])
@@ -247,9 +241,10 @@ int setup_device(dgw_solver *s) {
     {
         int ncu = 0;
         DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-        const int per_cu = split    ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
-                           : dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
-                                      : dgw::blocks_per_cu_3d(s->N);
+        const int per_cu = split ? (dim == 2 ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
+                                             : dgw::blocks_per_cu_3d_split(s->N))
+                                 : (dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
+                                             : dgw::blocks_per_cu_3d(s->N));
         const int ntiles = (int)(Kp / dgw::kTile);
         int ng = std::max(1, ncu) * per_cu;
         ng = std::min(ng, (ntiles + 7) / 8 * 8);
@@ -296,7 +291,9 @@ dgw::StageArgs stage_args(const dgw_solver *s) {
 }
 
 hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t st) {
-    if (s->opts.prec != DGW_FP32) return dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st);
+    if (s->opts.prec != DGW_FP32)
+        return s->dim == 2 ? dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st)
+                           : dgw::launch_stage3d_split(s->N, a, st);
     return dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, st);
 }
 
@@ -434,8 +431,8 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (!(opts.alpha >= 0.0 && opts.alpha <= 1.0)) return fail(DGW_EINVAL, "alpha must be in [0, 1]");
     if (opts.prec != DGW_FP32 && opts.prec != DGW_SPLIT_BF16 && opts.prec != DGW_SPLIT_FP16)
         return fail(DGW_EINVAL, "unknown precision variant");
-    if (opts.prec != DGW_FP32 && mesh->dim != 2)
-        return fail(DGW_EINVAL, "split-precision variants are implemented for 2D only");
+    if (opts.prec == DGW_SPLIT_FP16 && mesh->dim != 2)
+        return fail(DGW_EINVAL, "the 3D path has the FP32 and split-BF16 variants");
     if (opts.kernel < 0 || opts.kernel > 2) return fail(DGW_EINVAL, "kernel variant must be 0, 1 or 2");
     if (opts.prec != DGW_FP32 && opts.kernel == 1)
         return fail(DGW_EINVAL, "split-precision variants run on the matrix cores only (kernel 0 or 2)");
@@ -465,6 +462,10 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     s->nf = s->dim == 2 ? 3 : 6;
     s->K = mesh->n_elems;
     s->Kp = (s->K + dgw::kTile - 1) / dgw::kTile * dgw::kTile;
+    if (s->dim == 3 && (int64_t)s->nf * s->Np * s->Kp * 4 >= (int64_t(1) << 31)) {
+        delete s;
+        return fail(DGW_ETOOBIG, "3D field arrays are limited to 2 GiB (partner traces use 32-bit byte offsets)");
+    }
     for (int64_t k = 0; k < s->K; ++k)
         if (s->g.eps[k] != 1.0 || s->g.mu[k] != 1.0) s->material = true;
     if (s->dim == 3 && s->material) {

@@ -51,9 +51,11 @@ struct TriS {
     static constexpr int Np = (N + 1) * (N + 2) / 2;
     static constexpr int Nfp = N + 1;
     static constexpr int Nafp = 3 * Nfp;
-    static constexpr int Kd = 2 * Np + Nafp;
-    static constexpr int KS = (Kd + 31) / 32;  // K-steps of 32
+    static constexpr int KV = (Np + 31) / 32;    // K-steps of 32 of a derivative
+    static constexpr int KF = (Nafp + 31) / 32;  // K-steps of 32 of LIFT
     static constexpr int MT = (Np + 15) / 16;
+    static constexpr int FV = 2 * MT * KV * 64;  // Dr, Ds fragments (uint4 = 8 x 16 bit per lane)
+    static constexpr int FA = FV + MT * KF * 64; // + LIFT fragments: offset of the lo parts
     static constexpr int G = MAT ? 6 : 4;
     static constexpr int FG = MAT ? 6 : 3;
     static constexpr int RP = 3 * Np;          // partner traces / flux rows
@@ -68,6 +70,32 @@ struct TriS {
     }
 };
 
+// Op_hi b_hi + Op_hi b_lo + Op_lo b_hi accumulated on c.
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma3(uint4 ahu, uint4 alu, typename P16<PREC>::V bh, typename P16<PREC>::V bl,
+                                         floatx4 c) {
+    typename P16<PREC>::V ah, al;
+    __builtin_memcpy(&ah, &ahu, 16);
+    __builtin_memcpy(&al, &alu, 16);
+    c = P16<PREC>::mfma(ah, bh, c);
+    c = P16<PREC>::mfma(ah, bl, c);
+    return P16<PREC>::mfma(al, bh, c);
+}
+
+// Power-of-two scale taking a column maximum mx (per lane group) below 2^14,
+// reduced over the four lane groups of the column.
+__device__ __forceinline__ void pow2_scale(float mx, float &scale, float &unscale) {
+    mx = fmaxf(mx, __shfl_xor(mx, 16));
+    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    scale = unscale = 1.f;
+    if (mx > 0.f && mx < 3.0e38f) {
+        int ex;
+        frexpf(mx, &ex);  // mx < 2^ex
+        scale = ldexpf(1.f, 14 - ex);
+        unscale = ldexpf(1.f, ex - 14);
+    }
+}
+
 }  // namespace
 
 template <int N, bool MAT, int PREC>
@@ -76,10 +104,11 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
     using H = P16<PREC>;
     typedef typename H::T h16;
     typedef typename H::V hv;
-    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, Kd = T::Kd, KS = T::KS, MT = T::MT;
+    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, KV = T::KV, KF = T::KF, MT = T::MT;
+    constexpr int FV = T::FV, FA = T::FA;
     constexpr int G = T::G, FG = T::FG, RP = T::RP, SUB = T::SUB, BUF = T::BUF, QW = T::QW, JW = T::JW;
     __shared__ float sbuf[2 * BUF];
-    __shared__ uint4 sa[2 * MT * KS * 64];  // A fragments: hi then lo, 8 x 16-bit per lane
+    __shared__ uint4 sa[2 * FA];  // operator fragments: hi parts, then lo parts
 
     const int lane0 = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -88,7 +117,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
 
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.opsfrag);
-        for (int i = threadIdx.x; i < 2 * MT * KS * 64; i += 512) sa[i] = src[i];
+        for (int i = threadIdx.x; i < 2 * FA; i += 512) sa[i] = src[i];
     }
 
     const int x = blockIdx.x & 7, bi = blockIdx.x >> 3, GB = gridDim.x >> 3;
@@ -236,108 +265,122 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                 }
             }
 
-            // split-precision contraction: K-steps of 32, lane group g holds
-            // rows 32 ks + 8 g + q, q = 0..7.  Dr and Ds annihilate constants,
-            // so the volume operand is formed from q - q(c) with c a node near
-            // the centroid: the split then represents the (small, for resolved
-            // fields) variation across the element instead of the field itself.
+            // ---- volume: D_r u and D_s u of each source field u by split
+            // MFMA (K-steps of 32, lane group g holds rows 32 ks + 8 g + q),
+            // then the chain rule and curl in FP64 on the results.  Dr and Ds
+            // annihilate constants, so the operand is u - u(c), c a node near
+            // the centroid: the split then carries the variation across the
+            // element (small for resolved fields) rather than the field.
             constexpr int CN = T::lat(N / 3, N / 3);
-            const float hx0 = B[(0 * Np + CN) * 16], hy0 = B[(1 * Np + CN) * 16], ez0 = B[(2 * Np + CN) * 16];
-            const double rxH = rx * imu, ryH = ry * imu, sxH = sx * imu, syH = sy * imu;
-            const double rxE = rx * ieps, ryE = ry * ieps, sxE = sx * ieps, syE = sy * ieps;
-            // FP16 (5-bit exponent) needs a per-element power-of-two scale:
-            // the operand column is scaled so that its largest entry is below
-            // 2^14 (no overflow of the hi part, lo parts kept out of the
-            // subnormal range for entries near the maximum), the result is
-            // scaled back exactly.  The bound: volume entries are at most
-            // 2 max|g| max|q - q_c|, flux entries are read as they are.
-            float scale = 1.f, unscale = 1.f;
-            if constexpr (PREC == 2) {
-                float mq = 0.f, mf = 0.f;
-#pragma unroll
-                for (int nb = 0; nb < (Np + 3) / 4; ++nb) {
-                    const int n = 4 * nb + g;
-                    if (n < Np) {
-                        mq = fmaxf(mq, fabsf(B[(0 * Np + n) * 16] - hx0));
-                        mq = fmaxf(mq, fabsf(B[(1 * Np + n) * 16] - hy0));
-                        mq = fmaxf(mq, fabsf(B[(2 * Np + n) * 16] - ez0));
-                    }
-                }
-#pragma unroll
-                for (int jb = 0; jb < (Nafp + 3) / 4; ++jb) {
-                    const int j = 4 * jb + g;
-                    if (j < Nafp) {
-#pragma unroll
-                        for (int f = 0; f < 3; ++f) mf = fmaxf(mf, fabsf(B[(RP + f * Nafp + j) * 16]));
-                    }
-                }
-                const double gmax = fmax(fmax(fabs(rx), fabs(ry)), fmax(fabs(sx), fabs(sy))) * fmax(ieps, imu);
-                float mx = fmaxf((float)(2.0 * gmax * (double)mq) * 1.0001f, mf);
-                mx = fmaxf(mx, __shfl_xor(mx, 16));
-                mx = fmaxf(mx, __shfl_xor(mx, 32));
-                if (mx > 0.f && mx < 3.0e38f) {
-                    int ex;
-                    frexpf(mx, &ex);  // mx < 2^ex
-                    const int e = 14 - ex;
-                    scale = ldexpf(1.f, e);
-                    unscale = ldexpf(1.f, -e);
-                }
-            }
-            floatx4 acc[3][MT];
+            float cv[3][MT][4];
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[f][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                hv bh[3], bl[3];
+                    for (int jj = 0; jj < 4; ++jj) cv[f][mt][jj] = 0.f;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    // kmin/kmax bound k over the four lane groups at compile
-                    // time, so only straddling K-steps select per lane
-                    const int kmin = 32 * ks + q, kmax = kmin + 24;
-                    const int k = kmin + 8 * g;
-                    const bool vol = kmax < 2 * Np ? true : (kmin >= 2 * Np ? false : k < 2 * Np);
-                    float val[3];
-                    if (vol) {
-                        const bool isr = kmax < Np ? true : (kmin >= Np ? false : k < Np);
-                        const int node = isr ? k : k - Np;
-                        const double hx = B[(0 * Np + node) * 16] - hx0, hy = B[(1 * Np + node) * 16] - hy0;
-                        const double ez = B[(2 * Np + node) * 16] - ez0;
-                        const double uH = isr ? rxH : sxH, vH = isr ? ryH : syH;
-                        const double uE = isr ? rxE : sxE, vE = isr ? ryE : syE;
-                        val[0] = (float)(-vH * ez) * scale;
-                        val[1] = (float)(uH * ez) * scale;
-                        val[2] = (float)(uE * hy - vE * hx) * scale;
-                    } else if (k < Kd) {
-                        const int jf = k - 2 * Np;
+            for (int sf = 0; sf < 3; ++sf) {  // Hx, Hy, Ez
+                const float uc = B[(sf * Np + CN) * 16];
+                // FP16 (5-bit exponent): scale the operand column by a power of
+                // two so that its largest entry is below 2^14, undo it exactly
+                float scale = 1.f, unscale = 1.f;
+                if constexpr (PREC == 2) {
+                    float mx = 0.f;
 #pragma unroll
-                        for (int f = 0; f < 3; ++f) val[f] = B[(RP + f * Nafp + jf) * 16] * scale;
-                    } else {
-                        val[0] = val[1] = val[2] = 0.f;
+                    for (int nb = 0; nb < (Np + 3) / 4; ++nb) {
+                        const int n = 4 * nb + g;
+                        if (n < Np) mx = fmaxf(mx, fabsf(B[(sf * Np + n) * 16] - uc));
+                    }
+                    pow2_scale(mx, scale, unscale);
+                }
+                floatx4 d[2][MT];
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) d[p][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                int la = lane;
+                asm volatile("" : "+v"(la));
+#pragma unroll
+                for (int ks = 0; ks < KV; ++ks) {
+                    hv bh, bl;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int k = 32 * ks + 8 * g + q;
+                        const float v = k < Np ? (B[(sf * Np + k) * 16] - uc) * scale : 0.f;
+                        const h16 hi = (h16)v;
+                        bh[q] = hi;
+                        bl[q] = (h16)(v - (float)hi);
                     }
 #pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        const h16 hi = (h16)val[f];
-                        bh[f][q] = hi;
-                        bl[f][q] = (h16)(val[f] - (float)hi);
-                    }
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const int fi = ((p * MT + mt) * KV + ks) * 64 + la;
+                            d[p][mt] = mfma3<PREC>(sa[fi], sa[FA + fi], bh, bl, d[p][mt]);
+                        }
                 }
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const uint4 ahu = sa[(mt * KS + ks) * 64 + lane];
-                    const uint4 alu = sa[MT * KS * 64 + (mt * KS + ks) * 64 + lane];
-                    hv ah, al;
-                    __builtin_memcpy(&ah, &ahu, 16);
-                    __builtin_memcpy(&al, &alu, 16);
+                for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        acc[f][mt] = H::mfma(ah, bh[f], acc[f][mt]);
-                        acc[f][mt] = H::mfma(ah, bl[f], acc[f][mt]);
-                        acc[f][mt] = H::mfma(al, bh[f], acc[f][mt]);
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const double dr = (double)(d[0][mt][jj] * unscale), ds = (double)(d[1][mt][jj] * unscale);
+                        const double dx = rx * dr + sx * ds, dy = ry * dr + sy * ds;
+                        if (sf == 0) cv[2][mt][jj] -= (float)(ieps * dy);  // Ez -= dy Hx / eps
+                        if (sf == 1) cv[2][mt][jj] += (float)(ieps * dx);  // Ez += dx Hy / eps
+                        if (sf == 2) {
+                            cv[0][mt][jj] -= (float)(imu * dy);  // Hx -= dy Ez / mu
+                            cv[1][mt][jj] += (float)(imu * dx);  // Hy += dx Ez / mu
+                        }
                     }
-                }
+                // materialise the sums here (not sunk to the update)
+#pragma unroll
+                for (int o = 0; o < 3; ++o)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) asm volatile("" : "+v"(cv[o][mt][jj]));
                 __builtin_amdgcn_sched_barrier(0);
+            }
+
+            // ---- LIFT of the flux rows (split MFMA), on top of the volume part
+            floatx4 acc[3][MT];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                float scale = 1.f, unscale = 1.f;
+                if constexpr (PREC == 2) {
+                    float mx = 0.f;
+#pragma unroll
+                    for (int jb = 0; jb < (Nafp + 3) / 4; ++jb) {
+                        const int jn = 4 * jb + g;
+                        if (jn < Nafp) mx = fmaxf(mx, fabsf(B[(RP + f * Nafp + jn) * 16]));
+                    }
+                    pow2_scale(mx, scale, unscale);
+                }
+                floatx4 t[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) t[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KF; ++ks) {
+                    hv bh, bl;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int k = 32 * ks + 8 * g + q;
+                        const float v = k < Nafp ? B[(RP + f * Nafp + k) * 16] * scale : 0.f;
+                        const h16 hi = (h16)v;
+                        bh[q] = hi;
+                        bl[q] = (h16)(v - (float)hi);
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const int fi = FV + (mt * KF + ks) * 64 + lane;
+                        t[mt] = mfma3<PREC>(sa[fi], sa[FA + fi], bh, bl, t[mt]);
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[f][mt][jj] = cv[f][mt][jj] + t[mt][jj] * unscale;
             }
 
             // fused low-storage RK update
@@ -350,7 +393,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                         const int n = 16 * mt + 4 * g + jj;
                         if (n < Np) {
                             const unsigned idx = (unsigned)((f * Np + n) * 64 + col);
-                            const float r = A.a * rr[f][mt][jj] + A.dt * (acc[f][mt][jj] * unscale);
+                            const float r = A.a * rr[f][mt][jj] + A.dt * acc[f][mt][jj];
                             rt[idx] = r;
                             ot[idx] = B[(f * Np + n) * 16] + A.b * r;
                         }
@@ -431,33 +474,42 @@ static float from_f16_bits(uint16_t b) {
     return (float)h;
 }
 
-// out: 2*MT*KS*64 uint4 (hi fragments, then lo fragments); fragment (mt, ks)
-// of lane l holds Op[16 mt + l%16][32 ks + 8 (l/16) + q], q = 0..7.
-int opsfrag_split(int dim, int N, int prec, const double *ops_fused, int Kd, void *out) {
-    const int Np = dim == 2 ? (N + 1) * (N + 2) / 2 : (N + 1) * (N + 2) * (N + 3) / 6;
-    const int KS = (Kd + 31) / 32, MT = (Np + 15) / 16;
-    const int n = 2 * MT * KS * 64;
-    if (!out) return n * 16;
+// Operator fragments of the 2D split kernel, hi parts then lo parts, each
+// [Dr blocks (mt, ks < KV)][Ds blocks][LIFT blocks (mt, ks < KF)] x 64 lanes
+// x 8 values: lane l of block (mt, ks) holds M[16 mt + l%16][32 ks + 8 (l/16) + q]
+// (zero outside M).  Returns the size in bytes (out == nullptr: size only).
+int opsfrag2d_split(int N, int prec, const double *Dr, const double *Ds, const double *LIFT, void *out) {
+    const int Np = (N + 1) * (N + 2) / 2, Nafp = 3 * (N + 1);
+    const int MT = (Np + 15) / 16, KV = (Np + 31) / 32, KF = (Nafp + 31) / 32;
+    const int FV = 2 * MT * KV * 64, FA = FV + MT * KF * 64;
+    const size_t total = (size_t)2 * FA * 16;
+    if (!out) return (int)total;
     uint16_t *o = static_cast<uint16_t *>(out);
+    auto put = [&](size_t frag, const double *M, int cols, int mt, int ks, int l) {
+        for (int q = 0; q < 8; ++q) {
+            const int row = 16 * mt + (l % 16), k = 32 * ks + 8 * (l / 16) + q;
+            const double v = (row < Np && k < cols) ? M[(size_t)row * cols + k] : 0.0;
+            uint16_t hi, lo;
+            if (prec == 1) {
+                hi = to_bf16_bits((float)v);
+                lo = to_bf16_bits((float)(v - (double)from_bf16_bits(hi)));
+            } else {
+                hi = to_f16_bits((float)v);
+                lo = to_f16_bits((float)(v - (double)from_f16_bits(hi)));
+            }
+            o[frag * 8 + q] = hi;
+            o[(size_t)FA * 8 + frag * 8 + q] = lo;
+        }
+    };
+    const double *D[2] = {Dr, Ds};
+    for (int p = 0; p < 2; ++p)
+        for (int mt = 0; mt < MT; ++mt)
+            for (int ks = 0; ks < KV; ++ks)
+                for (int l = 0; l < 64; ++l) put((size_t)((p * MT + mt) * KV + ks) * 64 + l, D[p], Np, mt, ks, l);
     for (int mt = 0; mt < MT; ++mt)
-        for (int ks = 0; ks < KS; ++ks)
-            for (int l = 0; l < 64; ++l)
-                for (int q = 0; q < 8; ++q) {
-                    const int row = 16 * mt + (l % 16), k = 32 * ks + 8 * (l / 16) + q;
-                    const double v = (row < Np && k < Kd) ? ops_fused[(size_t)row * Kd + k] : 0.0;
-                    uint16_t hi, lo;
-                    if (prec == 1) {
-                        hi = to_bf16_bits((float)v);
-                        lo = to_bf16_bits((float)(v - (double)from_bf16_bits(hi)));
-                    } else {
-                        hi = to_f16_bits((float)v);
-                        lo = to_f16_bits((float)(v - (double)from_f16_bits(hi)));
-                    }
-                    const size_t base = ((size_t)(mt * KS + ks) * 64 + l) * 8 + q;
-                    o[base] = hi;
-                    o[(size_t)MT * KS * 64 * 8 + base] = lo;
-                }
-    return n * 16;
+        for (int ks = 0; ks < KF; ++ks)
+            for (int l = 0; l < 64; ++l) put((size_t)FV + (mt * KF + ks) * 64 + l, LIFT, Nafp, mt, ks, l);
+    return (int)total;
 }
 
 }  // namespace dgw

@@ -2,27 +2,30 @@
 // the element-local contractions on the matrix cores (v_mfma_f32_16x16x4_f32).
 //
 // 3D analogue of eq. dg-strong-explicit (section "Adding Generality": the
-// kernels change only mildly): with the fused operator Op = [Dr | Ds | Dt |
-// LIFT] (Np x (3 Np + 4 Nfp)) and g_p = (p_x, p_y, p_z) the gradient of the
-// reference coordinate p in {r, s, t} (constant on an affine element),
-//   curl E = sum_p D_p (g_p x E),
-// so each output field is one contraction:
-//   rhs_H = Op [-(g_r x E); -(g_s x E); -(g_t x E); flux_H]
-//   rhs_E = Op [ (g_r x H);  (g_s x H);  (g_t x H); flux_E]
-// with the upwind flux (3D form of eq. max2d-numflux, factor 1/2):
-//   flux_H = Fscale/2 ( n x [E] + alpha (n (n.[H]) - [H]) )
-//   flux_E = Fscale/2 (-n x [H] + alpha (n (n.[E]) - [E]) ).
+// kernels change only mildly).  Per element and stage:
+//   1. reference derivatives D_p u (p = r, s, t) of each of the six fields u
+//      (MFMA: [Dr; Ds; Dt] against the field's nodal values);
+//   2. chain rule and curl on those derivatives (eq. dg-diff-local-to-global,
+//      g_p = grad p constant per affine element):
+//        rhs_H = -curl E,  rhs_E = curl H,  d_x u = sum_p (p_x) D_p u, ...;
+//   3. upwind flux at every face node (3D form of eq. max2d-numflux, factor
+//      1/2, [q] = q- - q+):
+//        flux_H = Fscale/2 ( n x [E] + alpha (n (n.[H]) - [H]) )
+//        flux_E = Fscale/2 (-n x [H] + alpha (n (n.[E]) - [E]) ),
+//      the partner trace through the face record and the orientation table,
+//      on the PEC wall the mirror state E+ = -E-, H+ = H-;
+//   4. rhs += LIFT flux (MFMA), then res <- a res + dt rhs,
+//      q_out <- q_in + b res.
 //
-// Work-group = 4 waves, tile = 64 consecutive elements, wave w owns the MFMA
-// N-tile of elements 16w..16w+15.  (1) All waves stage the tile's fields and
-// the partner traces of every face node in LDS (the partner's node through
-// the face record and the orientation table; on the PEC wall the mirror state
-// E+ = -E-, H+ = H-).  (2) Each wave evaluates the flux of its 16 elements in
-// place of their partner traces.  (3) Contraction over the volume and flux
-// columns, the A fragments of Op streamed from L1/L2 several K-steps ahead.
-// The kernel is persistent: a work-group walks a contiguous run of tiles of
-// its XCD's share of the mesh.
-// (4) res <- a res + dt rhs, q_out <- q_in + b res.
+// Work unit = one wave and 16 consecutive elements (one MFMA N-tile; lane
+// (g, c) = (lane / 16, lane % 16) works on element column c).  Operands are
+// read straight from HBM (no LDS staging of fields): the B fragment of
+// K-step ks is rows 4 ks + g of the field, a 64-byte piece of each of four
+// 256-byte rows, and the four waves of a work-group take the four quarters
+// of one 64-element tile together.  The LDS holds only the operator
+// fragments and the face-node tables, so several work-groups share a CU and
+// their waves hide each other's memory latency.  Persistent grid with
+// XCD-contiguous ranges of tiles.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -38,229 +41,241 @@ struct Tet {
     static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
     static constexpr int Nfp = (N + 1) * (N + 2) / 2;
     static constexpr int Nafp = 4 * Nfp;
-    static constexpr int Kd = 3 * Np + Nafp;
-    static constexpr int KS = (Kd + 3) / 4;
-    static constexpr int MT = (Np + 15) / 16;
-    static constexpr int RP = 6 * Np;        // partner-trace / flux rows start
-    static constexpr int R = RP + 6 * Nafp;  // LDS rows of the tile
-    static constexpr int SUB = R * 16 + ((R & 1) ? 0 : 16);
+    static constexpr int MT = (Np + 15) / 16;   // M-tiles of the output nodes
+    static constexpr int KV = (Np + 3) / 4;     // K-steps of a derivative
+    static constexpr int KL = (Nafp + 3) / 4;   // K-steps of LIFT
+    static constexpr int AV = 3 * MT * KV * 64; // derivative fragments (floats)
+    static constexpr int AL = MT * KL * 64;     // LIFT fragments
     static constexpr int NT = Nafp + 4 * 6 * Nfp;  // face-node tables
 };
+
+// Buffer resource over `bytes` bytes at a wave-uniform base: loads through it
+// take one per-lane 32-bit offset plus a scalar offset (the row), so rows of
+// a tile share one address register; accesses past `bytes` read 0 / drop.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
 
 }  // namespace
 
 template <int N>
-__global__ void __launch_bounds__(256) stage3d_kernel(StageArgs A) {
+__global__ void __launch_bounds__(256, 2) stage3d_kernel(StageArgs A) {
     using T = Tet<N>;
-    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, Kd = T::Kd, KS = T::KS, MT = T::MT;
-    constexpr int RP = T::RP, SUB = T::SUB, NT = T::NT;
-    __shared__ float sq[4 * SUB];
+    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, MT = T::MT, KV = T::KV, KL = T::KL;
+    constexpr int AV = T::AV, AL = T::AL, NT = T::NT;
+    __shared__ float sA[AV + AL];
     __shared__ int stab[NT];
+
+    for (int i = threadIdx.x; i < AV + AL; i += 256) sA[i] = A.opsfrag[i];
+    for (int i = threadIdx.x; i < NT; i += 256) stab[i] = A.itab[i];
+    __syncthreads();
 
     const int lane0 = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g0 = lane0 >> 4, c0 = lane0 & 15;
-    const int col0 = 16 * w + c0;
 
-    for (int i = threadIdx.x; i < NT; i += 256) stab[i] = A.itab[i];
-
-    // tiles of this XCD: a contiguous range, dealt round-robin to its groups
+    // wave-tiles u = 4 tile + quarter; each XCD walks a contiguous range, the
+    // four waves of a work-group take the four quarters of one tile
+    const int nu = 4 * A.ntiles;
     const int x = blockIdx.x & 7, bi = blockIdx.x >> 3, GB = gridDim.x >> 3;
-    const int q8 = A.ntiles >> 3, r8 = A.ntiles & 7;
+    const int q8 = nu >> 3, r8 = nu & 7;
     const int xbase = x * q8 + (x < r8 ? x : r8), xcount = q8 + (x < r8 ? 1 : 0);
-    for (int tl = bi; tl < xcount; tl += GB) {
-    const int tile = xbase + tl;
-    __syncthreads();  // previous tile's readers of the LDS tile are done
-    // lane indices opaque to the compiler: per-lane offsets are recomputed per
-    // tile instead of being hoisted out of the tile loop into long-lived registers
-    int lane = lane0, col = col0, g = g0, c = c0;
-    asm volatile("" : "+v"(lane), "+v"(col), "+v"(g), "+v"(c));
-
-    // ---- (1) stage fields and partner traces (lane <-> element `lane`).
-    // Loads are issued in compile-time batches so that a whole batch is in
-    // flight before the first of its LDS stores waits.
-    {
-        constexpr int QW = (6 * Np + 3) / 4;  // field rows per wave
-        constexpr int QB = 28;                // rows per batch
-        constexpr int JW = (Nafp + 3) / 4;    // face nodes per wave
-        constexpr int JB = 5;                 // face nodes per batch (x6 fields)
-        const float *qt = A.qin + (size_t)tile * (6 * Np * 64);
-        float *L = sq + (lane >> 4) * SUB + (lane & 15);
-        const int *nt = A.nbr + (size_t)tile * (4 * 64);
-        int rec[4];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) rec[f] = nt[(unsigned)(f * 64 + lane)];
-#pragma unroll
-        for (int i0 = 0; i0 < QW; i0 += QB) {
-            float v[QB];
-#pragma unroll
-            for (int i = 0; i < QB; ++i) {
-                const int r = w + 4 * (i0 + i);
-                v[i] = (i0 + i < QW && r < 6 * Np) ? qt[(unsigned)(r * 64 + lane)] : 0.f;
-            }
-#pragma unroll
-            for (int i = 0; i < QB; ++i) {
-                const int r = w + 4 * (i0 + i);
-                if (i0 + i < QW && r < 6 * Np) L[r * 16] = v[i];
-            }
-        }
-        __syncthreads();  // stab visible
-#pragma unroll
-        for (int j0 = 0; j0 < JW; j0 += JB) {
-            float v[JB][6];
-            bool wl[JB];
-#pragma unroll
-            for (int jj = 0; jj < JB; ++jj) {
-                const int j = w + 4 * (j0 + jj);
-                wl[jj] = false;
-#pragma unroll
-                for (int f = 0; f < 6; ++f) v[jj][f] = 0.f;
-                if (j0 + jj < JW && j < Nafp) {
-                    const int face = j / Nfp, i = j - face * Nfp;
-                    const int rc = face == 0 ? rec[0] : face == 1 ? rec[1] : face == 2 ? rec[2] : rec[3];
-                    const bool wall = rc < 0;
-                    const int e2 = wall ? tile * 64 + lane : (rc >> 5);
-                    const int pn = wall ? stab[j] : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
-                    const unsigned q0 = ((unsigned)(e2 >> 6) * (6 * Np) + pn) * 64 + (e2 & 63);
-#pragma unroll
-                    for (int f = 0; f < 6; ++f) v[jj][f] = A.qin[q0 + f * Np * 64];
-                    wl[jj] = wall;
-                }
-            }
-#pragma unroll
-            for (int jj = 0; jj < JB; ++jj) {
-                const int j = w + 4 * (j0 + jj);
-                if (j0 + jj < JW && j < Nafp) {
-#pragma unroll
-                    for (int f = 0; f < 6; ++f)  // PEC mirror: E+ = -E-, H+ = H-
-                        L[(RP + f * Nafp + j) * 16] = (wl[jj] && f >= 3) ? -v[jj][f] : v[jj][f];
-                }
-            }
-        }
-    }
-
-    // per-column data of this wave's 16 elements
-    const float *gt = A.geo + (size_t)tile * (9 * 64);
-    float G[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) G[q] = gt[(unsigned)(q * 64 + col)];
-    const float *ft = A.fgeo + (size_t)tile * (16 * 64);
-    float FD[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) FD[q] = ft[(unsigned)(q * 64 + col)];
-    __syncthreads();
-
-    float *B = sq + w * SUB + c;  // this wave's sub-tile, column c
-
-    // ---- (2) upwind flux of this wave's elements, in place of the partner traces
     const float ha = 0.5f * A.alpha;
-    for (int jb = 0; jb < (Nafp + 3) / 4; ++jb) {
-        const int j = 4 * jb + g;
-        if (j < Nafp) {
-            const int face = j / Nfp;
-            const int own = stab[j];
-            float m[6], d[6];
+
+    for (int ul = 4 * bi + w; ul < xcount; ul += 4 * GB) {
+        const int u = xbase + ul;
+        const int tile = u >> 2;
+        // lane indices opaque to the compiler: per-lane offsets are recomputed
+        // per work unit rather than hoisted into long-lived registers
+        int lane = lane0;
+        asm volatile("" : "+v"(lane));
+        const int g = lane >> 4, c = lane & 15;
+        const int col = 16 * (u & 3) + c;
+        constexpr unsigned TB = 6 * Np * 64 * 4;  // bytes of a tile's fields
+        const __amdgpu_buffer_rsrc_t rq = rsrc(A.qin + (size_t)tile * (6 * Np * 64), TB);
+        const unsigned vcol = (unsigned)col * 4;             // column within a row
+        const unsigned vrow = (unsigned)(g * 64 + col) * 4;  // row 4 ks + g of a K-step
+
+        float G[9];
+        {
+            const __amdgpu_buffer_rsrc_t rg = rsrc(A.geo + (size_t)tile * (9 * 64), 9 * 64 * 4);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) G[q] = bload(rg, vcol, q * 256);
+        }
+
+        // volume part of the right-hand side, in plain registers
+        float cv[6][MT][4];
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) cv[f][mt][jj] = 0.f;
+
+        // ---- volume: derivatives of field f, then their curl contributions
+        float bq[KV], bn[KV];
+        // rows past Np belong to the next field (or lie past the tile, read
+        // as 0): their operator columns are zero, so they need no masking
+#pragma unroll
+        for (int ks = 0; ks < KV; ++ks) bn[ks] = bload(rq, vrow, (0 * Np + 4 * ks) * 256);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+#pragma unroll
+            for (int ks = 0; ks < KV; ++ks) bq[ks] = bn[ks];
+            if (f + 1 < 6) {  // next field's operand in flight during this one
+#pragma unroll
+                for (int ks = 0; ks < KV; ++ks) bn[ks] = bload(rq, vrow, ((f + 1) * Np + 4 * ks) * 256);
+            }
+            floatx4 d[3][MT];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) d[p][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // the operator fragments are re-read from LDS for every field: an
+            // index opaque to the compiler keeps it from holding all of them
+            // in registers across the six fields
+            int la = lane;
+            asm volatile("" : "+v"(la));
+#pragma unroll
+            for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        d[p][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[((p * MT + mt) * KV + ks) * 64 + la],
+                                                                       bq[ks], d[p][mt], 0, 0, 0);
+            // chain rule: d_x u = r_x D_r u + s_x D_s u + t_x D_t u, ...
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const float dr = d[0][mt][jj], ds = d[1][mt][jj], dtt = d[2][mt][jj];
+                    const float gx = G[0] * dr + G[3] * ds + G[6] * dtt;
+                    const float gy = G[1] * dr + G[4] * ds + G[7] * dtt;
+                    const float gz = G[2] * dr + G[5] * ds + G[8] * dtt;
+                    // fields 0..5 = Hx, Hy, Hz, Ex, Ey, Ez
+                    if (f == 0) { cv[4][mt][jj] += gz; cv[5][mt][jj] -= gy; }  // Ey += dz Hx, Ez -= dy Hx
+                    if (f == 1) { cv[3][mt][jj] -= gz; cv[5][mt][jj] += gx; }  // Ex -= dz Hy, Ez += dx Hy
+                    if (f == 2) { cv[3][mt][jj] += gy; cv[4][mt][jj] -= gx; }  // Ex += dy Hz, Ey -= dx Hz
+                    if (f == 3) { cv[1][mt][jj] -= gz; cv[2][mt][jj] += gy; }  // Hy -= dz Ex, Hz += dy Ex
+                    if (f == 4) { cv[0][mt][jj] += gz; cv[2][mt][jj] -= gx; }  // Hx += dz Ey, Hz -= dx Ey
+                    if (f == 5) { cv[0][mt][jj] -= gy; cv[1][mt][jj] += gx; }  // Hx -= dy Ez, Hy += dx Ez
+                }
+            // materialise the sums here: otherwise they are sunk to their use
+            // in the update and every field's derivatives stay live until then
+#pragma unroll
+            for (int o = 0; o < 6; ++o)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) asm volatile("" : "+v"(cv[o][mt][jj]));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // ---- surface: flux at face node j = 4 ks + g, then LIFT.  Face data
+        // of this element as scalars (no per-lane array indexing)
+        const __amdgpu_buffer_rsrc_t rn = rsrc(A.nbr + (size_t)tile * (4 * 64), 4 * 64 * 4);
+        const __amdgpu_buffer_rsrc_t rf = rsrc(A.fgeo + (size_t)tile * (16 * 64), 16 * 64 * 4);
+        auto face_rec = [&](int face) {
+            return __builtin_bit_cast(int, bload(rn, vcol, face * 256));
+        };
+        // all partner traces through one resource over the field array
+        const __amdgpu_buffer_rsrc_t rall = rsrc(A.qin, (unsigned)A.ntiles * TB);
+        // own and partner traces of face node j (on the wall the partner is
+        // the element itself; the mirror sign is applied with the jump)
+        auto load_traces = [&](int ks, float (&m)[6], float (&pv)[6], int &wall) {
+            const int j = 4 * ks + g;
+            const int jc = j < Nafp ? j : Nafp - 1;  // lanes past the faces read a valid node
+            const int face = jc / Nfp, i = jc - face * Nfp;
+            const int own = stab[jc];
+            const int rc = face_rec(face);
+            wall = rc < 0;
+            const int e2 = wall ? tile * 64 + col : (rc >> 5);
+            const int pn = wall ? own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
+            const unsigned vp = (((unsigned)(e2 >> 6) * (6 * Np) + pn) * 64 + (e2 & 63)) * 4;
+            const unsigned vo = (unsigned)(own * 64 + col) * 4;
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                m[f] = B[(f * Np + own) * 16];
-                d[f] = m[f] - B[(RP + f * Nafp + j) * 16];
+                m[f] = bload(rq, vo, f * Np * 256);
+                pv[f] = bload(rall, vp, f * Np * 256);
             }
-            const float nx = face == 0 ? FD[0] : face == 1 ? FD[4] : face == 2 ? FD[8] : FD[12];
-            const float ny = face == 0 ? FD[1] : face == 1 ? FD[5] : face == 2 ? FD[9] : FD[13];
-            const float nz = face == 0 ? FD[2] : face == 1 ? FD[6] : face == 2 ? FD[10] : FD[14];
-            const float fs = face == 0 ? FD[3] : face == 1 ? FD[7] : face == 2 ? FD[11] : FD[15];
+        };
+        // the LIFT contraction accumulates on top of the volume part
+        floatx4 acc[6][MT];
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[f][mt] = floatx4{cv[f][mt][0], cv[f][mt][1], cv[f][mt][2], cv[f][mt][3]};
+        float m[6], pv[6], mn[6], pn6[6];
+        int wall, walln;
+        load_traces(0, mn, pn6, walln);
+#pragma unroll
+        for (int ks = 0; ks < KL; ++ks) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                m[f] = mn[f];
+                pv[f] = pn6[f];
+            }
+            wall = walln;
+            if (ks + 1 < KL) load_traces(ks + 1, mn, pn6, walln);
+            const int j = 4 * ks + g;
+            const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
+            // [q] = q- - q+, with q+ = (H-, -E-) on the wall
+            float d[6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) d[f] = m[f] - ((wall && f >= 3) ? -pv[f] : pv[f]);
+            const float nx = bload(rf, vcol, (4 * face + 0) * 256);
+            const float ny = bload(rf, vcol, (4 * face + 1) * 256);
+            const float nz = bload(rf, vcol, (4 * face + 2) * 256);
+            const float fs = bload(rf, vcol, (4 * face + 3) * 256);
             const float dHx = d[0], dHy = d[1], dHz = d[2], dEx = d[3], dEy = d[4], dEz = d[5];
             const float ndH = nx * dHx + ny * dHy + nz * dHz;
             const float ndE = nx * dEx + ny * dEy + nz * dEz;
-            const float h = 0.5f * fs, ah = ha * fs;
-            // n x [E], n x [H]
+            const float h = j < Nafp ? 0.5f * fs : 0.f, ah = j < Nafp ? ha * fs : 0.f;
             const float cEx = ny * dEz - nz * dEy, cEy = nz * dEx - nx * dEz, cEz = nx * dEy - ny * dEx;
             const float cHx = ny * dHz - nz * dHy, cHy = nz * dHx - nx * dHz, cHz = nx * dHy - ny * dHx;
-            B[(RP + 0 * Nafp + j) * 16] = h * cEx + ah * (nx * ndH - dHx);
-            B[(RP + 1 * Nafp + j) * 16] = h * cEy + ah * (ny * ndH - dHy);
-            B[(RP + 2 * Nafp + j) * 16] = h * cEz + ah * (nz * ndH - dHz);
-            B[(RP + 3 * Nafp + j) * 16] = -h * cHx + ah * (nx * ndE - dEx);
-            B[(RP + 4 * Nafp + j) * 16] = -h * cHy + ah * (ny * ndE - dEy);
-            B[(RP + 5 * Nafp + j) * 16] = -h * cHz + ah * (nz * ndE - dEz);
+            float fl[6];
+            fl[0] = h * cEx + ah * (nx * ndH - dHx);
+            fl[1] = h * cEy + ah * (ny * ndH - dHy);
+            fl[2] = h * cEz + ah * (nz * ndH - dHz);
+            fl[3] = -h * cHx + ah * (nx * ndE - dEx);
+            fl[4] = -h * cHy + ah * (ny * ndE - dEy);
+            fl[5] = -h * cHz + ah * (nz * ndE - dEz);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const float a = sA[AV + (mt * KL + ks) * 64 + lane];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) acc[f][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, fl[f], acc[f][mt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-    }
-    // the flux rows read below are this wave's own: LDS order within a wave suffices
 
-    // ---- (3) contraction on the matrix cores
-    floatx4 acc[6][MT];
-#pragma unroll
-    for (int f = 0; f < 6; ++f)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[f][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // The A fragments stream from L1/L2 through a PD-deep software pipeline
-    // (the LDS holds the tile; the whole operator does not fit in registers
-    // next to the 6 x MT accumulators).
-    constexpr int PD = 6;
-    float apipe[PD][MT];
-#pragma unroll
-    for (int d = 0; d < PD; ++d)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) apipe[d][mt] = d < KS ? A.opsfrag[(unsigned)((mt * KS + d) * 64 + lane)] : 0.f;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        float a[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            a[mt] = apipe[ks % PD][mt];
-            if (ks + PD < KS) apipe[ks % PD][mt] = A.opsfrag[(unsigned)((mt * KS + ks + PD) * 64 + lane)];
-        }
-        const int k = 4 * ks + g;
-        float b[6];
-        if (k < 3 * Np) {
-            const int p = k / Np, node = k - p * Np;
-            const float gx = p == 0 ? G[0] : p == 1 ? G[3] : G[6];
-            const float gy = p == 0 ? G[1] : p == 1 ? G[4] : G[7];
-            const float gz = p == 0 ? G[2] : p == 1 ? G[5] : G[8];
-            float v[6];
-#pragma unroll
-            for (int f = 0; f < 6; ++f) v[f] = B[(f * Np + node) * 16];
-            // -(g x E) for the H outputs, (g x H) for the E outputs
-            b[0] = -(gy * v[5] - gz * v[4]);
-            b[1] = -(gz * v[3] - gx * v[5]);
-            b[2] = -(gx * v[4] - gy * v[3]);
-            b[3] = gy * v[2] - gz * v[1];
-            b[4] = gz * v[0] - gx * v[2];
-            b[5] = gx * v[1] - gy * v[0];
-        } else if (k < Kd) {
-            const int j = k - 3 * Np;
-#pragma unroll
-            for (int f = 0; f < 6; ++f) b[f] = B[(RP + f * Nafp + j) * 16];
-        } else {
-#pragma unroll
-            for (int f = 0; f < 6; ++f) b[f] = 0.f;
-        }
+        // ---- fused low-storage RK update
+        const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (6 * Np * 64), TB);
+        const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (6 * Np * 64), TB);
+        const unsigned vout = (unsigned)(4 * g * 64 + col) * 4;  // row 16 mt + 4 g + jj
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int f = 0; f < 6; ++f)
-                acc[f][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], b[f], acc[f][mt], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-
-    // ---- (4) fused low-storage RK update
-    float *rt = A.res + (size_t)tile * (6 * Np * 64);
-    float *ot = A.qout + (size_t)tile * (6 * Np * 64);
+            for (int jj = 0; jj < 4; ++jj) {
+                const int n = 16 * mt + 4 * g + jj;
+                if (n < Np) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int n = 16 * mt + 4 * g + jj;
-            if (n < Np) {
-#pragma unroll
-                for (int f = 0; f < 6; ++f) {
-                    const unsigned idx = (unsigned)((f * Np + n) * 64 + col);
-                    const float r = A.a * rt[idx] + A.dt * acc[f][mt][jj];
-                    rt[idx] = r;
-                    ot[idx] = B[(f * Np + n) * 16] + A.b * r;
+                    for (int f = 0; f < 6; ++f) {
+                        const unsigned so = (f * Np + 16 * mt + jj) * 256;
+                        const float r = A.a * bload(rr, vout, so) + A.dt * acc[f][mt][jj];
+                        bstore(rr, r, vout, so);
+                        bstore(ro, bload(rq, vout, so) + A.b * r, vout, so);
+                    }
                 }
             }
-        }
-    }  // tile loop
+    }
 }
 
 template <int N>
@@ -305,30 +320,30 @@ const char *stage3d_kernel_name(int N) {
     return "stage3d_kernel<N>";
 }
 
-// Fragment-ordered copy of [Dr | Ds | Dt | LIFT] for the A operand:
-// out[(mt*KS + ks)*64 + l] = Op[16 mt + l%16][4 ks + l/16].
+// A-fragment order of the 3D kernel's operators: first Dr, Ds, Dt
+// (out[((p*MT + mt)*KV + ks)*64 + l] = D_p[16 mt + l%16][4 ks + l/16]), then
+// LIFT (out[AV + (mt*KL + ks)*64 + l] = LIFT[16 mt + l%16][4 ks + l/16]);
+// zero outside the matrices.  Returns the number of floats.
 int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, float *out) {
     const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 4 * ((N + 1) * (N + 2) / 2);
-    const int Kd = 3 * Np + Nafp, KS = (Kd + 3) / 4, MT = (Np + 15) / 16;
-    if (!out) return MT * KS * 64;
+    const int MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nafp + 3) / 4;
+    const int AV = 3 * MT * KV * 64, AL = MT * KL * 64;
+    if (!out) return AV + AL;
+    const double *D[3] = {Dr, Ds, Dt};
+    for (int p = 0; p < 3; ++p)
+        for (int mt = 0; mt < MT; ++mt)
+            for (int ks = 0; ks < KV; ++ks)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * mt + (l % 16), k = 4 * ks + l / 16;
+                    out[((p * MT + mt) * KV + ks) * 64 + l] = (row < Np && k < Np) ? (float)D[p][row * Np + k] : 0.f;
+                }
     for (int mt = 0; mt < MT; ++mt)
-        for (int ks = 0; ks < KS; ++ks)
+        for (int ks = 0; ks < KL; ++ks)
             for (int l = 0; l < 64; ++l) {
                 const int row = 16 * mt + (l % 16), k = 4 * ks + l / 16;
-                double v = 0.0;
-                if (row < Np && k < Kd) {
-                    if (k < Np)
-                        v = Dr[row * Np + k];
-                    else if (k < 2 * Np)
-                        v = Ds[row * Np + (k - Np)];
-                    else if (k < 3 * Np)
-                        v = Dt[row * Np + (k - 2 * Np)];
-                    else
-                        v = LIFT[row * Nafp + (k - 3 * Np)];
-                }
-                out[(mt * KS + ks) * 64 + l] = (float)v;
+                out[AV + (mt * KL + ks) * 64 + l] = (row < Np && k < Nafp) ? (float)LIFT[row * Nafp + k] : 0.f;
             }
-    return MT * KS * 64;
+    return AV + AL;
 }
 
 }  // namespace dgw

@@ -138,8 +138,8 @@ def test_error_paths_before_any_device_call():
     t = inputs.tet_grid(1)
     t.eps = np.full(t.K, 2.0)
     _expect("DGW_EINVAL", lambda: dgw.Solver(t, 2, device=-1))
-    # split precision: 2D only, matrix-core kernels only, known variants only
-    _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="split_bf16", device=-1))
+    # split precision: FP16 in 2D only, matrix-core kernels only, known variants only
+    _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="split_fp16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec="split_fp16", kernel=1, device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec=7, device=-1))
     # NULL arguments at the raw ABI

@@ -74,3 +74,54 @@ def test_3d_full_size_vs_closed_form():
         err = s.cavity_error(1, 1, 1, 1.0)
         print(f"3D 663552 tets to t=1 in {n} steps: rel L2 vs closed form {err:.2e}")
         assert err < 1e-5
+
+
+@pytest.mark.parametrize("n,N,seed,permute", [
+    (2, 1, 1, False),
+    (2, 2, 2, True),
+    (3, 3, 3, True),   # 162 tets: 3 tiles, ragged tail
+    (3, 4, 4, True),
+])
+def test_split_bf16_rhs_parity_3d(n, N, seed, permute):
+    """Split-BF16 3D stage: one right-hand side against the oracle.  The
+    operands carry ~2^-17 relative error per hi+lo split and the dropped
+    lo*lo term ~2^-18; with the cancellation of the reference derivatives
+    we allow 1e-4 (random data) and 5e-4 (smooth data)."""
+    m = inputs.tet_grid(n, seed=seed, permute=permute)
+    d = oracle.Discretization3D(m.vx, m.vy, m.vz, m.elem_verts, N)
+    op = oracle.Maxwell3D(d, 1.0)
+    sol = dgw.Solver(m, N, prec="split_bf16")
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal(sol.shape)
+    err = rel(sol.rhs(q), op.rhs(q))
+    q2 = oracle.cavity_mode_3d(d.x, d.y, d.z, 0.2)
+    err2 = rel(sol.rhs(q2), op.rhs(q2))
+    print(f"3D split_bf16 rhs n={n} N={N} K={m.K}: random {err:.2e}, smooth {err2:.2e}")
+    assert err < 1e-4
+    assert err2 < 5e-4
+
+
+def test_split_bf16_steps_3d():
+    m = inputs.tet_grid(3, seed=6, permute=True)
+    d = oracle.Discretization3D(m.vx, m.vy, m.vz, m.elem_verts, 4)
+    op = oracle.Maxwell3D(d, 1.0)
+    dt = cfl_dt(d, 4)
+    q0 = oracle.cavity_mode_3d(d.x, d.y, d.z, 0.0)
+    want = op.run(q0, dt, 30)
+    with dgw.Solver(m, 4, prec="split_bf16") as s:
+        s.set_fields(q0)
+        s.advance_steps(30, dt)
+        err = rel(s.get_fields(), want)
+    print(f"3D split_bf16 30 steps vs oracle: {err:.2e}")
+    assert err < 1e-4
+
+
+def test_3d_split_bf16_full_size_vs_closed_form():
+    """The 663552-tetrahedron cavity to t = 1 with the split-BF16 stage."""
+    m = inputs.tet_grid(48, seed=5)
+    with dgw.Solver(m, 4, prec="split_bf16") as s:
+        s.set_cavity_mode(1, 1, 1)
+        n = s.advance(1.0)
+        err = s.cavity_error(1, 1, 1, 1.0)
+        print(f"3D split_bf16 663552 tets to t=1 in {n} steps: rel L2 vs closed form {err:.2e}")
+        assert err < 1e-4
