@@ -248,7 +248,7 @@ def main():
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
-        kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false>"
+        kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false, false>"
     out = {
         "metric": METRIC,
         "value": value,

@@ -197,6 +197,32 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     }
     __syncthreads();
 
+    // consumers: the residual rows of their next tile are loaded at the end of
+    // the current one (they stay in flight across the barrier).  Up to N = 6
+    // this also frees enough registers for two resident work-groups per CU;
+    // at N = 7, 8 (one work-group either way) they are loaded at tile start
+    constexpr bool XRES = N <= 6;
+    float rrn[XRES ? 3 : 1][MT][4];
+    auto load_res = [&](int tile) {
+        const TileSrc S = tile_src<BATCH>(A, tile);
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int cl = 16 * w + (ln & 15), gl = ln >> 4;
+        const float *rt = S.res + (size_t)S.tile * (3 * Np * 64);
+        if constexpr (XRES) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int n = 16 * mt + 4 * gl + jj;
+                        rrn[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + cl)] : 0.f;
+                    }
+        }
+    };
+    if (XRES && !producer) load_res(xbase + bi);
+
     int it = 0;
     for (int tl = bi; tl < xcount; tl += GB, ++it) {
         const int cur = it & 1;
@@ -224,8 +250,12 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
-                        const int n = 16 * mt + 4 * g + jj;
-                        rr[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
+                        if constexpr (XRES) {
+                            rr[f][mt][jj] = rrn[f][mt][jj];
+                        } else {
+                            const int n = 16 * mt + 4 * g + jj;
+                            rr[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
+                        }
                     }
 
             const float rx = B[(RG + 0) * 16], ry = B[(RG + 1) * 16];
@@ -352,6 +382,7 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                             ot[idx] = B[(f * Np + n) * 16] + A.b * r;
                         }
                     }
+            if (XRES && tl + GB < xcount) load_res(xbase + tl + GB);
         }
         __syncthreads();
     }

@@ -185,6 +185,26 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
     }
     __syncthreads();
 
+    // consumers: the residual rows of their next tile are loaded at the end of
+    // the current one, so the update never waits on memory
+    float rrn[3][MT][4];
+    auto load_res = [&](int tile) {
+        int ln = lane0;
+        asm volatile("" : "+v"(ln));
+        const int col = 16 * w + (ln & 15), g = ln >> 4;
+        const float *rt = A.res + (size_t)tile * (3 * Np * 64);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int n = 16 * mt + 4 * g + jj;
+                    rrn[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
+                }
+    };
+    if (!producer) load_res(xbase + bi);
+
     int it = 0;
     for (int tl = bi; tl < xcount; tl += GB, ++it) {
         const int cur = it & 1;
@@ -210,10 +230,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) {
-                        const int n = 16 * mt + 4 * g + jj;
-                        rr[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
-                    }
+                    for (int jj = 0; jj < 4; ++jj) rr[f][mt][jj] = rrn[f][mt][jj];
             // FP64 geometric factors and face data of column col
             const double *gt = A.geo64 + (size_t)tile * (G * 64);
             const double rx = gt[0 * 64 + col], ry = gt[1 * 64 + col], sx = gt[2 * 64 + col], sy = gt[3 * 64 + col];
@@ -398,6 +415,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                             ot[idx] = B[(f * Np + n) * 16] + A.b * r;
                         }
                     }
+            if (tl + GB < xcount) load_res(xbase + tl + GB);
         }
         __syncthreads();
     }

@@ -64,8 +64,22 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 
 }  // namespace
 
+// Tuning: K-steps of face traces kept in flight, fields of volume operands
+// kept in flight, work-groups per CU the register allocation aims at.
+#ifndef DGW_3D_SPD
+#define DGW_3D_SPD 2
+#endif
+#ifndef DGW_3D_VPD
+#define DGW_3D_VPD 1
+#endif
+#ifndef DGW_3D_MINB
+#define DGW_3D_MINB 2
+#endif
+constexpr int SPD = DGW_3D_SPD;
+constexpr int VPD = DGW_3D_VPD;
+
 template <int N>
-__global__ void __launch_bounds__(256, 2) stage3d_kernel(StageArgs A) {
+__global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) {
     using T = Tet<N>;
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, MT = T::MT, KV = T::KV, KL = T::KL;
     constexpr int AV = T::AV, AL = T::AL, NT = T::NT;
@@ -118,18 +132,22 @@ __global__ void __launch_bounds__(256, 2) stage3d_kernel(StageArgs A) {
                 for (int jj = 0; jj < 4; ++jj) cv[f][mt][jj] = 0.f;
 
         // ---- volume: derivatives of field f, then their curl contributions
-        float bq[KV], bn[KV];
+        // operands of the next VPD fields in flight (a ring of registers);
         // rows past Np belong to the next field (or lie past the tile, read
         // as 0): their operator columns are zero, so they need no masking
+        float bring[VPD][KV];
 #pragma unroll
-        for (int ks = 0; ks < KV; ++ks) bn[ks] = bload(rq, vrow, (0 * Np + 4 * ks) * 256);
+        for (int f0 = 0; f0 < VPD; ++f0)
+#pragma unroll
+            for (int ks = 0; ks < KV; ++ks) bring[f0][ks] = bload(rq, vrow, (f0 * Np + 4 * ks) * 256);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
+            float bq[KV];
 #pragma unroll
-            for (int ks = 0; ks < KV; ++ks) bq[ks] = bn[ks];
-            if (f + 1 < 6) {  // next field's operand in flight during this one
+            for (int ks = 0; ks < KV; ++ks) bq[ks] = bring[f % VPD][ks];
+            if (f + VPD < 6) {
 #pragma unroll
-                for (int ks = 0; ks < KV; ++ks) bn[ks] = bload(rq, vrow, ((f + 1) * Np + 4 * ks) * 256);
+                for (int ks = 0; ks < KV; ++ks) bring[f % VPD][ks] = bload(rq, vrow, ((f + VPD) * Np + 4 * ks) * 256);
             }
             floatx4 d[3][MT];
 #pragma unroll
@@ -177,12 +195,21 @@ __global__ void __launch_bounds__(256, 2) stage3d_kernel(StageArgs A) {
             __builtin_amdgcn_sched_barrier(0);
         }
 
-        // ---- surface: flux at face node j = 4 ks + g, then LIFT.  Face data
-        // of this element as scalars (no per-lane array indexing)
+        // ---- surface: flux at face node j = 4 ks + g, then LIFT.  The face
+        // records and face data of the element are loaded once, up front, and
+        // held as scalars (selected per lane, no per-lane array indexing): a
+        // load whose value is needed in the same step would make the step
+        // wait for every load issued before it, prefetched traces included
         const __amdgpu_buffer_rsrc_t rn = rsrc(A.nbr + (size_t)tile * (4 * 64), 4 * 64 * 4);
         const __amdgpu_buffer_rsrc_t rf = rsrc(A.fgeo + (size_t)tile * (16 * 64), 16 * 64 * 4);
-        auto face_rec = [&](int face) {
-            return __builtin_bit_cast(int, bload(rn, vcol, face * 256));
+        const int rc0 = __builtin_bit_cast(int, bload(rn, vcol, 0)), rc1 = __builtin_bit_cast(int, bload(rn, vcol, 256));
+        const int rc2 = __builtin_bit_cast(int, bload(rn, vcol, 512)), rc3 = __builtin_bit_cast(int, bload(rn, vcol, 768));
+        float fd[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) fd[q] = bload(rf, vcol, q * 256);
+        auto face_rec = [&](int face) { return face == 0 ? rc0 : face == 1 ? rc1 : face == 2 ? rc2 : rc3; };
+        auto face_val = [&](int face, int q) {
+            return face == 0 ? fd[q] : face == 1 ? fd[4 + q] : face == 2 ? fd[8 + q] : fd[12 + q];
         };
         // all partner traces through one resource over the field array
         const __amdgpu_buffer_rsrc_t rall = rsrc(A.qin, (unsigned)A.ntiles * TB);
@@ -212,28 +239,31 @@ __global__ void __launch_bounds__(256, 2) stage3d_kernel(StageArgs A) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 acc[f][mt] = floatx4{cv[f][mt][0], cv[f][mt][1], cv[f][mt][2], cv[f][mt][3]};
-        float m[6], pv[6], mn[6], pn6[6];
-        int wall, walln;
-        load_traces(0, mn, pn6, walln);
+        // traces of the next SPD K-steps in flight (a ring of registers)
+        float mb[SPD][6], pb[SPD][6];
+        int wb[SPD];
+#pragma unroll
+        for (int s0 = 0; s0 < SPD; ++s0)
+            if (s0 < KL) load_traces(s0, mb[s0], pb[s0], wb[s0]);
 #pragma unroll
         for (int ks = 0; ks < KL; ++ks) {
+            float m[6], pv[6];
+            const int slot = ks % SPD;
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                m[f] = mn[f];
-                pv[f] = pn6[f];
+                m[f] = mb[slot][f];
+                pv[f] = pb[slot][f];
             }
-            wall = walln;
-            if (ks + 1 < KL) load_traces(ks + 1, mn, pn6, walln);
+            const int wall = wb[slot];
+            if (ks + SPD < KL) load_traces(ks + SPD, mb[slot], pb[slot], wb[slot]);
             const int j = 4 * ks + g;
             const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
             // [q] = q- - q+, with q+ = (H-, -E-) on the wall
             float d[6];
 #pragma unroll
             for (int f = 0; f < 6; ++f) d[f] = m[f] - ((wall && f >= 3) ? -pv[f] : pv[f]);
-            const float nx = bload(rf, vcol, (4 * face + 0) * 256);
-            const float ny = bload(rf, vcol, (4 * face + 1) * 256);
-            const float nz = bload(rf, vcol, (4 * face + 2) * 256);
-            const float fs = bload(rf, vcol, (4 * face + 3) * 256);
+            const float nx = face_val(face, 0), ny = face_val(face, 1);
+            const float nz = face_val(face, 2), fs = face_val(face, 3);
             const float dHx = d[0], dHy = d[1], dHz = d[2], dEx = d[3], dEy = d[4], dEz = d[5];
             const float ndH = nx * dHx + ny * dHy + nz * dHz;
             const float ndE = nx * dEx + ny * dEy + nz * dEz;
@@ -260,21 +290,39 @@ __global__ void __launch_bounds__(256, 2) stage3d_kernel(StageArgs A) {
         const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (6 * Np * 64), TB);
         const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (6 * Np * 64), TB);
         const unsigned vout = (unsigned)(4 * g * 64 + col) * 4;  // row 16 mt + 4 g + jj
+        // per field: all loads, then all arithmetic, then the stores (a store
+        // between two loads orders them and exposes one memory latency per
+        // value).  Rows 16 mt + 4 g + jj >= Np read the next field's rows (or
+        // 0 past the tile) and are not stored.
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int f = 0; f < 6; ++f) {
+            float rv[MT][4], qv[MT][4];
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int n = 16 * mt + 4 * g + jj;
-                if (n < Np) {
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int f = 0; f < 6; ++f) {
+                for (int jj = 0; jj < 4; ++jj) {
+                    const unsigned so = (f * Np + 16 * mt + jj) * 256;
+                    rv[mt][jj] = bload(rr, vout, so);
+                    qv[mt][jj] = bload(rq, vout, so);
+                }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    rv[mt][jj] = A.a * rv[mt][jj] + A.dt * acc[f][mt][jj];
+                    qv[mt][jj] = qv[mt][jj] + A.b * rv[mt][jj];
+                }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (16 * mt + 4 * g + jj < Np) {
                         const unsigned so = (f * Np + 16 * mt + jj) * 256;
-                        const float r = A.a * bload(rr, vout, so) + A.dt * acc[f][mt][jj];
-                        bstore(rr, r, vout, so);
-                        bstore(ro, bload(rq, vout, so) + A.b * r, vout, so);
+                        bstore(rr, rv[mt][jj], vout, so);
+                        bstore(ro, qv[mt][jj], vout, so);
                     }
                 }
-            }
+        }
     }
 }
 

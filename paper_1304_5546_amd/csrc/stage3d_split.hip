@@ -70,6 +70,10 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
     constexpr int FV = T::FV, FL = T::FL, NT = T::NT;
     __shared__ uint4 sA[2 * (FV + FL)];  // hi fragments, then lo fragments
     __shared__ int stab[NT];
+    // per wave: the face records and FP64 face data (n, Fscale) of its 16
+    // elements, read per face node from LDS instead of memory
+    __shared__ double sfd[4][4][4][16];
+    __shared__ int srec[4][4][16];
 
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.opsfrag);
@@ -113,10 +117,29 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) cv[f][mt][jj] = 0.f;
 
-        // ---- volume
+        // ---- volume.  The next field's operand rows are in flight while the
+        // current field is contracted; rows past Np meet zero operator
+        // columns (values past the tile read as 0)
+        float vn[KV][8], qcn = bload(rq, vcol, (0 * Np + T::CN) * 256);
+#pragma unroll
+        for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) vn[ks][q] = bload(rq, vrow8, (0 * Np + 32 * ks + q) * 256);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            const float qc = bload(rq, vcol, (f * Np + T::CN) * 256);
+            float vc[KV][8];
+            const float qc = qcn;
+#pragma unroll
+            for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) vc[ks][q] = vn[ks][q];
+            if (f + 1 < 6) {
+                qcn = bload(rq, vcol, ((f + 1) * Np + T::CN) * 256);
+#pragma unroll
+                for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) vn[ks][q] = bload(rq, vrow8, ((f + 1) * Np + 32 * ks + q) * 256);
+            }
             floatx4 d[3][MT];
 #pragma unroll
             for (int p = 0; p < 3; ++p)
@@ -129,9 +152,7 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
                 bf16x8 bh, bl;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    // rows past Np meet zero operator columns (values past the
-                    // tile read as 0)
-                    const float v = bload(rq, vrow8, (f * Np + 32 * ks + q) * 256) - qc;
+                    const float v = vc[ks][q] - qc;
                     const __bf16 h = (__bf16)v;
                     bh[q] = h;
                     bl[q] = (__bf16)(v - (float)h);
@@ -172,39 +193,64 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
         // ---- surface
         const __amdgpu_buffer_rsrc_t rn = rsrc(A.nbr + (size_t)tile * (4 * 64), 4 * 64 * 4);
         const __amdgpu_buffer_rsrc_t rall = rsrc(A.qin, (unsigned)A.ntiles * TB);
-        const double *ft = A.fgeo64 + (size_t)tile * (16 * 64);
+        {
+            // lane group g fetches face g of its column
+            const double *ft = A.fgeo64 + (size_t)tile * (16 * 64);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sfd[w][g][q][c] = ft[(unsigned)((4 * g + q) * 64 + col)];
+            srec[w][g][c] = __builtin_bit_cast(int, bload(rn, vcol, g * 256));
+        }
         floatx4 acc[6][MT];
 #pragma unroll
         for (int f = 0; f < 6; ++f)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 acc[f][mt] = floatx4{cv[f][mt][0], cv[f][mt][1], cv[f][mt][2], cv[f][mt][3]};
+        // own and partner traces of face-node slot t = 8 ks + q (node
+        // j = 32 ks + 8 g + q); two slots in flight ahead of the one in use
+        auto gather = [&](int t, float (&m)[6], float (&pv)[6], int &wall) {
+            const int j = 32 * (t >> 3) + 8 * g + (t & 7);
+            const int jc = j < Nafp ? j : Nafp - 1;
+            const int face = jc / Nfp, i = jc - face * Nfp;
+            const int own = stab[jc];
+            const int rc = srec[w][face][c];
+            wall = rc < 0;
+            const int e2 = wall ? tile * 64 + col : (rc >> 5);
+            const int pn = wall ? own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
+            const unsigned vp = (((unsigned)(e2 >> 6) * (6 * Np) + pn) * 64 + (e2 & 63)) * 4;
+            const unsigned vo = (unsigned)(own * 64 + col) * 4;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                m[f] = bload(rq, vo, f * Np * 256);
+                pv[f] = bload(rall, vp, f * Np * 256);
+            }
+        };
+        constexpr int NS = 8 * KL, RING = 2;
+        float rm[RING][6], rp[RING][6];
+        int rw[RING];
+#pragma unroll
+        for (int t = 0; t < RING - 1; ++t)
+            if (t < NS) gather(t, rm[t], rp[t], rw[t]);
 #pragma unroll
         for (int ks = 0; ks < KL; ++ks) {
             bf16x8 bh[6], bl[6];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
+                const int t = 8 * ks + q;
+                if (t + RING - 1 < NS) gather(t + RING - 1, rm[(t + RING - 1) % RING], rp[(t + RING - 1) % RING],
+                                              rw[(t + RING - 1) % RING]);
                 const int j = 32 * ks + 8 * g + q;
                 const int jc = j < Nafp ? j : Nafp - 1;
-                const int face = jc / Nfp, i = jc - face * Nfp;
-                const int own = stab[jc];
-                const int rc = __builtin_bit_cast(int, bload(rn, vcol, face * 256));
-                const bool wall = rc < 0;
-                const int e2 = wall ? tile * 64 + col : (rc >> 5);
-                const int pn = wall ? own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
-                const unsigned vp = (((unsigned)(e2 >> 6) * (6 * Np) + pn) * 64 + (e2 & 63)) * 4;
-                const unsigned vo = (unsigned)(own * 64 + col) * 4;
+                const int face = jc / Nfp;
+                const bool wall = rw[t % RING] != 0;
                 double dq[6];
 #pragma unroll
                 for (int f = 0; f < 6; ++f) {
-                    const float m = bload(rq, vo, f * Np * 256);
-                    const float pv = bload(rall, vp, f * Np * 256);
-                    dq[f] = (double)m - ((wall && f >= 3) ? -(double)pv : (double)pv);
+                    const double m = rm[t % RING][f], pv = rp[t % RING][f];
+                    dq[f] = m - ((wall && f >= 3) ? -pv : pv);
                 }
-                const double nx = ft[(unsigned)((4 * face + 0) * 64 + col)];
-                const double ny = ft[(unsigned)((4 * face + 1) * 64 + col)];
-                const double nz = ft[(unsigned)((4 * face + 2) * 64 + col)];
-                const double fs = ft[(unsigned)((4 * face + 3) * 64 + col)];
+                const double nx = sfd[w][face][0][c], ny = sfd[w][face][1][c];
+                const double nz = sfd[w][face][2][c], fs = sfd[w][face][3][c];
                 const double dHx = dq[0], dHy = dq[1], dHz = dq[2], dEx = dq[3], dEy = dq[4], dEz = dq[5];
                 const double ndH = nx * dHx + ny * dHy + nz * dHz;
                 const double ndE = nx * dEx + ny * dEy + nz * dEz;
@@ -239,21 +285,39 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
         const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (6 * Np * 64), TB);
         const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (6 * Np * 64), TB);
         const unsigned vout = (unsigned)(4 * g * 64 + col) * 4;
+        // per field: all loads, then all arithmetic, then the stores (a store
+        // between two loads orders them and exposes one memory latency per
+        // value).  Rows 16 mt + 4 g + jj >= Np read the next field's rows (or
+        // 0 past the tile) and are not stored.
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int f = 0; f < 6; ++f) {
+            float rv[MT][4], qv[MT][4];
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int n = 16 * mt + 4 * g + jj;
-                if (n < Np) {
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int f = 0; f < 6; ++f) {
+                for (int jj = 0; jj < 4; ++jj) {
+                    const unsigned so = (f * Np + 16 * mt + jj) * 256;
+                    rv[mt][jj] = bload(rr, vout, so);
+                    qv[mt][jj] = bload(rq, vout, so);
+                }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    rv[mt][jj] = A.a * rv[mt][jj] + A.dt * acc[f][mt][jj];
+                    qv[mt][jj] = qv[mt][jj] + A.b * rv[mt][jj];
+                }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (16 * mt + 4 * g + jj < Np) {
                         const unsigned so = (f * Np + 16 * mt + jj) * 256;
-                        const float r = A.a * bload(rr, vout, so) + A.dt * acc[f][mt][jj];
-                        bstore(rr, r, vout, so);
-                        bstore(ro, bload(rq, vout, so) + A.b * r, vout, so);
+                        bstore(rr, rv[mt][jj], vout, so);
+                        bstore(ro, qv[mt][jj], vout, so);
                     }
                 }
-            }
+        }
     }
 }
 
