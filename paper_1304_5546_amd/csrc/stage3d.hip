@@ -18,14 +18,15 @@
 //      q_out <- q_in + b res.
 //
 // Work unit = one wave and 16 consecutive elements (one MFMA N-tile; lane
-// (g, c) = (lane / 16, lane % 16) works on element column c).  Operands are
-// read straight from HBM (no LDS staging of fields): the B fragment of
-// K-step ks is rows 4 ks + g of the field, a 64-byte piece of each of four
-// 256-byte rows, and the four waves of a work-group take the four quarters
-// of one 64-element tile together.  The LDS holds only the operator
-// fragments and the face-node tables, so several work-groups share a CU and
-// their waves hide each other's memory latency.  Persistent grid with
-// XCD-contiguous ranges of tiles.
+// (g, c) = (lane / 16, lane % 16) works on element column c).  The operands
+// of the derivatives are read straight from HBM (buffer loads sharing one
+// address register per lane): the B fragment of K-step ks is rows 4 ks + g
+// of the field, a 64-byte piece of each of four 256-byte rows; the eight
+// waves of a work-group take the quarters of two 64-element tiles together.
+// As they arrive the values are also written to the wave's LDS copy of its
+// elements' fields, from which the face traces and the update read them (no
+// second trip to memory).  The LDS also holds the operator fragments and the
+// face-node tables.  Persistent grid with XCD-contiguous ranges of tiles.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -65,57 +66,66 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 }  // namespace
 
 // Tuning: K-steps of face traces kept in flight, fields of volume operands
-// kept in flight, work-groups per CU the register allocation aims at.
+// kept in flight.
 #ifndef DGW_3D_SPD
 #define DGW_3D_SPD 2
 #endif
 #ifndef DGW_3D_VPD
 #define DGW_3D_VPD 1
 #endif
-#ifndef DGW_3D_MINB
-#define DGW_3D_MINB 2
-#endif
 constexpr int SPD = DGW_3D_SPD;
 constexpr int VPD = DGW_3D_VPD;
 
 template <int N>
-__global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) {
+__global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     using T = Tet<N>;
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, MT = T::MT, KV = T::KV, KL = T::KL;
     constexpr int AV = T::AV, AL = T::AL, NT = T::NT;
     __shared__ float sA[AV + AL];
     __shared__ int stab[NT];
+    // each wave's copy of its 16 elements' fields, [field * Np + node][17]
+    // (row stride 17: rows of different lane groups fall in different banks);
+    // the face traces and the update read the element's own values here
+    // instead of from memory again
+    constexpr int FS = 17;
+    __shared__ float sF[8][6 * Np * FS];
 
-    for (int i = threadIdx.x; i < AV + AL; i += 256) sA[i] = A.opsfrag[i];
-    for (int i = threadIdx.x; i < NT; i += 256) stab[i] = A.itab[i];
+    for (int i = threadIdx.x; i < AV + AL; i += 512) sA[i] = A.opsfrag[i];
+    for (int i = threadIdx.x; i < NT; i += 512) stab[i] = A.itab[i];
     __syncthreads();
 
     const int lane0 = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    // wave-tiles u = 4 tile + quarter; each XCD walks a contiguous range, the
-    // four waves of a work-group take the four quarters of one tile
-    const int nu = 4 * A.ntiles;
+    // the work-group takes two consecutive tiles at a time (wave w: tile
+    // 2 p + w / 4, quarter w % 4); each XCD walks a contiguous range of tile
+    // pairs.  The loop bound is uniform over the work-group (it meets two
+    // barriers per pair); a wave whose tile lies past the mesh idles.
+    const int npairs = (A.ntiles + 1) >> 1;
     const int x = blockIdx.x & 7, bi = blockIdx.x >> 3, GB = gridDim.x >> 3;
-    const int q8 = nu >> 3, r8 = nu & 7;
+    const int q8 = npairs >> 3, r8 = npairs & 7;
     const int xbase = x * q8 + (x < r8 ? x : r8), xcount = q8 + (x < r8 ? 1 : 0);
     const float ha = 0.5f * A.alpha;
 
-    for (int ul = 4 * bi + w; ul < xcount; ul += 4 * GB) {
-        const int u = xbase + ul;
-        const int tile = u >> 2;
+    float *F = sF[w];
+    for (int pl = bi; pl < xcount; pl += GB) {
+        const int pair = xbase + pl;
+        const int tile = 2 * pair + (w >> 2);
+        const bool active = tile < A.ntiles;  // wave-uniform
         // lane indices opaque to the compiler: per-lane offsets are recomputed
         // per work unit rather than hoisted into long-lived registers
         int lane = lane0;
         asm volatile("" : "+v"(lane));
         const int g = lane >> 4, c = lane & 15;
-        const int col = 16 * (u & 3) + c;
+        const int col = 16 * (w & 3) + c;
         constexpr unsigned TB = 6 * Np * 64 * 4;  // bytes of a tile's fields
         const __amdgpu_buffer_rsrc_t rq = rsrc(A.qin + (size_t)tile * (6 * Np * 64), TB);
         const unsigned vcol = (unsigned)col * 4;             // column within a row
         const unsigned vrow = (unsigned)(g * 64 + col) * 4;  // row 4 ks + g of a K-step
 
         float G[9];
+        float cv[6][MT][4];
+        if (active) {
         {
             const __amdgpu_buffer_rsrc_t rg = rsrc(A.geo + (size_t)tile * (9 * 64), 9 * 64 * 4);
 #pragma unroll
@@ -123,7 +133,6 @@ __global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) 
         }
 
         // volume part of the right-hand side, in plain registers
-        float cv[6][MT][4];
 #pragma unroll
         for (int f = 0; f < 6; ++f)
 #pragma unroll
@@ -144,7 +153,10 @@ __global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) 
         for (int f = 0; f < 6; ++f) {
             float bq[KV];
 #pragma unroll
-            for (int ks = 0; ks < KV; ++ks) bq[ks] = bring[f % VPD][ks];
+            for (int ks = 0; ks < KV; ++ks) {
+                bq[ks] = bring[f % VPD][ks];
+                if (4 * ks + g < Np) F[(f * Np + 4 * ks + g) * FS + c] = bq[ks];
+            }
             if (f + VPD < 6) {
 #pragma unroll
                 for (int ks = 0; ks < KV; ++ks) bring[f % VPD][ks] = bload(rq, vrow, ((f + VPD) * Np + 4 * ks) * 256);
@@ -194,6 +206,11 @@ __global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) 
                     for (int jj = 0; jj < 4; ++jj) asm volatile("" : "+v"(cv[o][mt][jj]));
             __builtin_amdgcn_sched_barrier(0);
         }
+        }  // active
+        // every wave's LDS copy of its fields is complete: partner traces of
+        // elements in this pair of tiles are read from there
+        __syncthreads();
+        if (active) {
 
         // ---- surface: flux at face node j = 4 ks + g, then LIFT.  The face
         // records and face data of the element are loaded once, up front, and
@@ -225,11 +242,16 @@ __global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) 
             const int e2 = wall ? tile * 64 + col : (rc >> 5);
             const int pn = wall ? own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
             const unsigned vp = (((unsigned)(e2 >> 6) * (6 * Np) + pn) * 64 + (e2 & 63)) * 4;
-            const unsigned vo = (unsigned)(own * 64 + col) * 4;
+            const int t2 = (e2 >> 6) - 2 * pair;  // partner tile within the pair?
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                m[f] = bload(rq, vo, f * Np * 256);
-                pv[f] = bload(rall, vp, f * Np * 256);
+            for (int f = 0; f < 6; ++f) m[f] = F[(f * Np + own) * FS + c];
+            if ((unsigned)t2 < 2u) {
+                const float *F2 = sF[4 * t2 + ((e2 & 63) >> 4)];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pv[f] = F2[(f * Np + pn) * FS + (e2 & 15)];
+            } else {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pv[f] = bload(rall, vp, f * Np * 256);
             }
         };
         // the LIFT contraction accumulates on top of the volume part
@@ -303,7 +325,8 @@ __global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) 
                 for (int jj = 0; jj < 4; ++jj) {
                     const unsigned so = (f * Np + 16 * mt + jj) * 256;
                     rv[mt][jj] = bload(rr, vout, so);
-                    qv[mt][jj] = bload(rq, vout, so);
+                    const int n = 16 * mt + 4 * g + jj;
+                    qv[mt][jj] = n < Np ? F[(f * Np + n) * FS + c] : 0.f;
                 }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -323,6 +346,8 @@ __global__ void __launch_bounds__(256, DGW_3D_MINB) stage3d_kernel(StageArgs A) 
                     }
                 }
         }
+        }  // active
+        __syncthreads();  // the LDS copies are read by other waves until here
     }
 }
 
@@ -332,14 +357,14 @@ static hipError_t launch3d(const StageArgs &a, hipStream_t s) {
     if (!a.opsfrag || !a.itab || !a.qin || !a.qout || !a.res || !a.geo || !a.fgeo || !a.nbr || a.ntiles <= 0 ||
         a.ngroups < 8 || (a.ngroups & 7))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage3d_kernel<N>), dim3(a.ngroups), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((stage3d_kernel<N>), dim3(a.ngroups), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
 template <int N>
 static int occupancy3d() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage3d_kernel<N>, 256, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage3d_kernel<N>, 512, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
