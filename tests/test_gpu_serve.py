@@ -167,3 +167,24 @@ def test_cancel_and_destroy_in_flight():
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 30
+
+
+def test_serving_mix_small_requests_vs_oracle():
+    """Requests of the seeded serving mix with s <= 32 (their full t_final,
+    their disk inclusions) through the server, each against the FP64 oracle
+    at the server's dt and step count."""
+    reqs = [r for r in inputs.make_requests(256, seed=4) if r.s <= 32][:3]
+    assert len(reqs) == 3
+    with dgw.Server() as srv:
+        tickets = [srv.submit(inputs.request_mesh(r), r.order, mode=r.mode, t_final=r.t_final, keep_fields=True)
+                   for r in reqs]
+        results = [srv.wait(t, fields=True) for t in tickets]
+    for r, (res, q) in zip(reqs, results):
+        assert res["status"] == "DGW_OK"
+        m = inputs.request_mesh(r)
+        d = oracle.Discretization2D(m.vx, m.vy, m.elem_verts, r.order, eps=m.eps, mu=m.mu)
+        op = oracle.Maxwell2D(d, 1.0)
+        want = op.run(oracle.cavity_mode_2d(d.x, d.y, 0.0, *r.mode), res["dt"], res["steps"])
+        err = rel(q, want)
+        print(f"mix request {r.index}: s={r.s} N={r.order} t_final={r.t_final:.3f} steps={res['steps']}: {err:.2e}")
+        assert err < 1e-5
