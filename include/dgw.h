@@ -265,7 +265,8 @@ int dgw_cancel(dgw_server *srv, uint64_t ticket);
  * device-busy seconds they took (summed chunk times). */
 int dgw_server_stats(dgw_server *srv, int64_t *completed, double *dof_updates, double *busy_s);
 /* Cancel everything not finished, wait for the workers, free the device
- * memory.  Uncollected results are discarded. */
+ * memory.  Uncollected results are discarded.  No other call on this server
+ * may be in progress, or made afterwards. */
 void dgw_server_destroy(dgw_server *srv);
 
 #ifdef __cplusplus

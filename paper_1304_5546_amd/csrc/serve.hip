@@ -138,13 +138,24 @@ void admit_locked(dgw_server *S) {
             continue;
         }
         if (S->slots_used >= S->opts.max_slots || S->reserved + r->footprint > S->opts.hbm_budget_bytes) break;
+        // queue the set-up first (it may throw; the worker waits for this
+        // lock before it looks at the request)
+        push_task(S, [S, r] { setup(S, r); });
         S->pending.pop_front();
         S->slots_used++;
         S->reserved += r->footprint;
         S->setups_in_flight++;
         r->st = St::Setup;
         r->res.t_admit = S->now();
-        push_task(S, [S, r] { setup(S, r); });
+    }
+}
+
+// Admission that never throws: a failed task allocation leaves the queue as
+// it was, admission is retried at the next event.
+void admit_nothrow(dgw_server *S) {
+    try {
+        admit_locked(S);
+    } catch (...) {
     }
 }
 
@@ -211,8 +222,12 @@ void finalize(dgw_server *S, Req *r, int status) {
             r->res.rel_l2_mode = err;
         }
         if (rc == DGW_OK && r->keep) {
-            r->fields.resize((size_t)3 * r->K * r->s->Np);
-            rc = dgw_get_fields(r->s, r->fields.data());
+            try {
+                r->fields.resize((size_t)3 * r->K * r->s->Np);
+                rc = dgw_get_fields(r->s, r->fields.data());
+            } catch (const std::bad_alloc &) {
+                rc = DGW_ENOMEM;
+            }
         }
         if (rc == DGW_OK && !std::isfinite(r->res.energy)) rc = DGW_ENONFINITE;
         status = rc;
@@ -226,7 +241,7 @@ void finalize(dgw_server *S, Req *r, int status) {
     S->slots_used--;
     if (status == DGW_OK) S->completed++;
     end_locked(S, r, status);
-    admit_locked(S);
+    admit_nothrow(S);
     S->cv_sched.notify_all();
 }
 
@@ -239,7 +254,7 @@ void worker_loop(dgw_server *S) {
         auto fn = std::move(S->tasks.front());
         S->tasks.pop_front();
         lk.unlock();
-        fn();
+        fn();  // tasks catch their own exceptions
         lk.lock();
     }
 }
@@ -348,6 +363,17 @@ int run_chunk(dgw_server *S, const std::vector<Req *> &batch, int64_t chunk) {
 void sched_loop(dgw_server *S) {
     hipSetDevice(S->opts.device);
     std::unique_lock<std::mutex> lk(S->mu);
+    // hand a request that leaves the device to a worker (or finish it here
+    // if the task cannot be queued)
+    auto hand_off = [&](Req *r, int st) {
+        try {
+            push_task(S, [S, r, st] { finalize(S, r, st); });
+        } catch (...) {
+            lk.unlock();
+            finalize(S, r, st);
+            lk.lock();
+        }
+    };
     for (;;) {
         S->cv_sched.wait(lk, [&] {
             return !S->ready.empty() || !S->running.empty() || (S->stop && S->setups_in_flight == 0);
@@ -370,7 +396,7 @@ void sched_loop(dgw_server *S) {
                 ++i;
             }
         }
-        for (Req *r : leaving) push_task(S, [S, r] { finalize(S, r, DGW_ECANCELLED); });
+        for (Req *r : leaving) hand_off(r, DGW_ECANCELLED);
         if (S->running.empty()) {
             if (S->stop && S->setups_in_flight == 0 && S->ready.empty()) return;
             continue;
@@ -397,8 +423,7 @@ void sched_loop(dgw_server *S) {
                 leave = r->steps_left == 0;
             }
             if (leave) {
-                const int st = rc;
-                push_task(S, [S, r, st] { finalize(S, r, st); });
+                hand_off(r, rc);
                 S->running.erase(S->running.begin() + i);
             } else {
                 ++i;
@@ -518,6 +543,12 @@ int dgw_submit(dgw_server *S, const dgw_request *q, uint64_t *ticket) {
         delete r;
         return dgw::set_error(DGW_ECANCELLED, "server is shutting down");
     }
+    try {
+        S->reqs.reserve(S->reqs.size() + 1);
+    } catch (const std::bad_alloc &) {
+        delete r;
+        return dgw::set_error(DGW_ENOMEM, "host allocation failed");
+    }
     if (r->footprint > S->opts.hbm_budget_bytes) {
         const int64_t fp = r->footprint;
         delete r;
@@ -525,10 +556,16 @@ int dgw_submit(dgw_server *S, const dgw_request *q, uint64_t *ticket) {
     }
     r->id = S->next_id++;
     r->res.t_arrival = S->now();
-    S->reqs[r->id] = r;
-    S->pending.push_back(r);
+    try {
+        S->reqs[r->id] = r;
+        S->pending.push_back(r);
+    } catch (const std::bad_alloc &) {
+        S->reqs.erase(r->id);
+        delete r;
+        return dgw::set_error(DGW_ENOMEM, "host allocation failed");
+    }
     *ticket = r->id;
-    admit_locked(S);
+    admit_nothrow(S);  // may queue set-up tasks
     return DGW_OK;
 }
 
@@ -546,9 +583,15 @@ int dgw_wait(dgw_server *S, uint64_t ticket, double *q_out, dgw_result *res) {
     std::unique_lock<std::mutex> lk(S->mu);
     auto it = S->reqs.find(ticket);
     if (it == S->reqs.end()) return dgw::set_error(DGW_ENOTFOUND, "unknown ticket");
+    if (q_out && !it->second->keep) return dgw::set_error(DGW_EINVAL, "fields requested but keep_fields was 0");
+    // look the ticket up again on every wake-up: another thread waiting on
+    // the same ticket may have collected it meanwhile
+    S->cv_done.wait(lk, [&] {
+        it = S->reqs.find(ticket);
+        return it == S->reqs.end() || it->second->st == St::Done;
+    });
+    if (it == S->reqs.end()) return dgw::set_error(DGW_ENOTFOUND, "ticket collected by another caller");
     Req *r = it->second;
-    if (q_out && !r->keep) return dgw::set_error(DGW_EINVAL, "fields requested but keep_fields was 0");
-    S->cv_done.wait(lk, [&] { return r->st == St::Done; });
     if (res) *res = r->res;
     if (q_out && r->res.status == DGW_OK) std::copy(r->fields.begin(), r->fields.end(), q_out);
     const int status = r->res.status;
@@ -569,7 +612,7 @@ int dgw_cancel(dgw_server *S, uint64_t ticket) {
     if (r->st == St::Pending) {
         S->pending.erase(std::find(S->pending.begin(), S->pending.end(), r));
         end_locked(S, r, DGW_ECANCELLED);
-        admit_locked(S);
+        admit_nothrow(S);
     }
     S->cv_sched.notify_all();
     return DGW_OK;
@@ -590,7 +633,7 @@ void dgw_server_destroy(dgw_server *S) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
         for (auto &kv : S->reqs) kv.second->cancel = true;
-        admit_locked(S);  // ends every pending request as cancelled
+        admit_nothrow(S);  // ends every pending request as cancelled (no task is queued on stop)
     }
     S->cv_sched.notify_all();
     if (S->sched.joinable()) S->sched.join();
