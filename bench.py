@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel", type=int, default=0, help="stage kernel: 0 auto, 1 scalar-operand VALU, 2 MFMA")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "split_bf16", "split_fp16"],
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "split_bf16", "split_fp16", "fp64"],
                     help="arithmetic of the timed path (value and roofline)")
     ap.add_argument("--serve", action="store_true", help="run the serving configuration instead")
     ap.add_argument("--serve-n", type=int, default=256, help="requests in the serving run")
@@ -245,13 +245,15 @@ def main():
     value = dofs * args.steps / (ms * 1e-3)
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
-    pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2}[args.prec]
+    pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2, "fp64": 3}[args.prec]
     if dim == 3:
         kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
+    elif pcode == 3:
+        kname = f"stage2d_kernel<double, {N}, false>" if args.kernel == 1 else f"stage2d_f64_kernel<{N}, false>"
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
-        kname = f"stage2d_kernel<{N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false, false>"
+        kname = f"stage2d_kernel<float, {N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false, false>"
     out = {
         "metric": METRIC,
         "value": value,
@@ -263,7 +265,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if pcode == 0 else ("bf16x2+f32acc" if pcode == 1 else "f16x2+f32acc"),
+        "dtype": ["f32", "bf16x2+f32acc", "f16x2+f32acc", "f64"][pcode],
         "data": "synthetic",
         "config": {"workload": desc, "K": solver.K, "N": N, "Np": solver.Np, "dofs": dofs, "dt": dt,
                    "t_reached": t_reached, "precision": args.prec},
@@ -279,7 +281,7 @@ def main():
         # the same timed run for every precision variant, each with its
         # relative L2 error against the closed-form mode at t = 1
         var = {}
-        for prec in ("fp32", "split_bf16", "split_fp16") if dim == 2 else ("fp32", "split_bf16"):
+        for prec in ("fp32", "split_bf16", "split_fp16", "fp64") if dim == 2 else ("fp32", "split_bf16"):
             if prec == args.prec:
                 v_ms, v_err = ms, err
             else:

@@ -81,17 +81,24 @@ typedef struct {
     const double *eps, *mu;
 } dgw_mesh;
 
-/* Arithmetic of the stage contractions.  Fields are FP32 in every variant.
+/* Arithmetic of the stage.  Fields are FP32 in the first three variants.
  * The split variants evaluate each Op*B product (Op = [Dr | Ds | LIFT]) as
  * Op_hi*B_hi + Op_hi*B_lo + Op_lo*B_hi in 16-bit parts with FP32
  * accumulation on the matrix cores, and keep the geometric factors, normals
- * and surface Jacobians in FP64 on the device; 2D only (dgw_create returns
- * DGW_EINVAL for a 3D mesh, or with kernel = 1).  Measured accuracy is
- * stated beside every result (relative L2 against the FP64 reference). */
+ * and surface Jacobians in FP64 on the device (split-FP16: 2D only; neither
+ * with kernel = 1).  DGW_FP64 (section "Adding Generality", item "Double
+ * Precision": the method run with double-precision fields) keeps the
+ * fields, the RK residual, the operators, the factors and every operation
+ * of the stage in FP64 (kernel 0 or 2: FP64 matrix cores; 1: the
+ * scalar-operand kernel); 2D only, and the FP32 device-pointer calls
+ * (dgw_set_fields_dev, dgw_get_fields_dev) return DGW_EINVAL for it.
+ * Measured accuracy is stated beside every result (relative L2 against
+ * the FP64 reference). */
 typedef enum {
     DGW_FP32 = 0,        /* all contractions in FP32                              */
     DGW_SPLIT_BF16 = 1,  /* Dr/Ds/LIFT as BF16 hi+lo split products, FP32 accum.  */
-    DGW_SPLIT_FP16 = 2   /* same with FP16 hi+lo split products                   */
+    DGW_SPLIT_FP16 = 2,  /* same with FP16 hi+lo split products                   */
+    DGW_FP64 = 3         /* FP64 fields and arithmetic throughout (2D)            */
 } dgw_precision;
 
 typedef struct {
@@ -181,7 +188,7 @@ int dgw_last_info(const dgw_solver *s, dgw_info *info);
 /* Device-pointer plumbing for callers holding FP32 device buffers (e.g. torch
  * tensors): q_dev is [n_fields][K][Np] FP32 in caller order on the solver's
  * device, stream a hipStream_t (NULL = solver stream).  Asynchronous on that
- * stream. */
+ * stream.  DGW_EINVAL for a DGW_FP64 solver. */
 int dgw_set_fields_dev(dgw_solver *s, const float *q_dev, void *stream);
 int dgw_get_fields_dev(dgw_solver *s, float *q_dev, void *stream);
 /* Launch `nsteps` steps on `stream` without waiting (for timing by the

@@ -26,7 +26,17 @@ __device__ double block_sum(double v, double *sh) {
     return s;
 }
 
+// field value i as FP64, from the FP32 or the FP64 field array
+template <bool D64, typename Args>
+__device__ __forceinline__ double qval(const Args &a, size_t i) {
+    if constexpr (D64)
+        return a.q64[i];
+    else
+        return (double)a.q[i];
+}
+
 // one thread per element: sum_f w_f q_f^T M q_f J
+template <bool D64>
 __global__ void __launch_bounds__(kRedThreads) energy_kernel(ReduceArgs a) {
     __shared__ double sh[kRedThreads / 64];
     double acc = 0.0;
@@ -35,9 +45,9 @@ __global__ void __launch_bounds__(kRedThreads) energy_kernel(ReduceArgs a) {
         for (int f = 0; f < a.nf; ++f) {
             double qf = 0.0;
             for (int i = 0; i < a.Np; ++i) {
-                const double qi = a.q[tix(e, f * a.Np + i, a.nf * a.Np)];
+                const double qi = qval<D64>(a, tix(e, f * a.Np + i, a.nf * a.Np));
                 double mq = 0.0;
-                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * (double)a.q[tix(e, f * a.Np + j, a.nf * a.Np)];
+                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * qval<D64>(a, tix(e, f * a.Np + j, a.nf * a.Np));
                 qf += qi * mq;
             }
             ek += (a.w ? a.w[tix(e, f, a.nf)] : 1.0) * qf;
@@ -80,6 +90,7 @@ __device__ void cavity_exact(const CavityArgs &a, double x, double y, double z, 
     }
 }
 
+template <bool D64>
 __global__ void cavity_init_kernel(CavityArgs a) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int nf = a.dim == 2 ? 3 : 6;
@@ -90,13 +101,20 @@ __global__ void cavity_init_kernel(CavityArgs a) {
             const size_t p = tix(e, i, a.Np);
             cavity_exact(a, a.x[p], a.y[p], a.dim == 3 ? a.z[p] : 0.0, out);
         }
-        for (int f = 0; f < nf; ++f) a.q[tix(e, f * a.Np + i, nf * a.Np)] = (float)out[f];
+        for (int f = 0; f < nf; ++f) {
+            const size_t p = tix(e, f * a.Np + i, nf * a.Np);
+            if constexpr (D64)
+                a.q64[p] = out[f];
+            else
+                a.q[p] = (float)out[f];
+        }
     }
 }
 
 // one thread per element; accumulates ||q - q_exact||^2_M and ||q_exact||^2_M
 // (the closed form is re-evaluated inside the M product instead of being
 // stored, keeping the kernel free of large per-lane arrays)
+template <bool D64>
 __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a) {
     __shared__ double sh[kRedThreads / 64];
     const int nf = a.dim == 2 ? 3 : 6;
@@ -107,14 +125,14 @@ __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a)
             const size_t pi = tix(e, i, a.Np);
             double exi[6], di[6], md[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
             cavity_exact(a, a.x[pi], a.y[pi], a.dim == 3 ? a.z[pi] : 0.0, exi);
-            for (int f = 0; f < nf; ++f) di[f] = (double)a.q[tix(e, f * a.Np + i, nf * a.Np)] - exi[f];
+            for (int f = 0; f < nf; ++f) di[f] = qval<D64>(a, tix(e, f * a.Np + i, nf * a.Np)) - exi[f];
             for (int j = 0; j < a.Np; ++j) {
                 const size_t pj = tix(e, j, a.Np);
                 double exj[6];
                 cavity_exact(a, a.x[pj], a.y[pj], a.dim == 3 ? a.z[pj] : 0.0, exj);
                 const double Mij = a.Mref[i * a.Np + j];
                 for (int f = 0; f < nf; ++f) {
-                    md[f] += Mij * ((double)a.q[tix(e, f * a.Np + j, nf * a.Np)] - exj[f]);
+                    md[f] += Mij * (qval<D64>(a, tix(e, f * a.Np + j, nf * a.Np)) - exj[f]);
                     mx[f] += Mij * exj[f];
                 }
             }
@@ -157,18 +175,31 @@ __global__ void to_caller_kernel(const float *src, float *dst, const int *perm, 
 
 }  // namespace
 
+// Each launch reads (or writes) q64 when it is set, else q.
 hipError_t launch_energy(const ReduceArgs &a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(energy_kernel, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    if (!a.q && !a.q64) return hipErrorInvalidValue;
+    if (a.q64)
+        hipLaunchKernelGGL(energy_kernel<true>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(energy_kernel<false>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cavity_init(const CavityArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(cavity_init_kernel, dim3((a.Kp + 255) / 256), dim3(256), 0, s, a);
+    if (!a.q && !a.q64) return hipErrorInvalidValue;
+    if (a.q64)
+        hipLaunchKernelGGL(cavity_init_kernel<true>, dim3((a.Kp + 255) / 256), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(cavity_init_kernel<false>, dim3((a.Kp + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cavity_error(const CavityArgs &a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(cavity_error_kernel, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    if (!a.q && !a.q64) return hipErrorInvalidValue;
+    if (a.q64)
+        hipLaunchKernelGGL(cavity_error_kernel<true>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(cavity_error_kernel<false>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@
 // per-element array is tiled, [tile][row][64] (see tix()), so that one wave's
 // 64 lanes (64 consecutive elements of a tile) read one row as 256
 // contiguous bytes:
-//   q, res  : rows f*Np + n, FP32 (n_fields*Np rows)
+//   q, res  : rows f*Np + n, FP32 (n_fields*Np rows; FP64 in FP64 solvers)
 //   geo     : G rows of per-element factors: 2D r_x, r_y, s_x, s_y (+ 1/eps,
 //             1/mu with materials); 3D the nine entries of A_k^{-1}
 //   fgeo    : Nfaces*FG rows of per-face data, row face*FG + q: 2D n_x, n_y,
@@ -63,6 +63,14 @@ struct StageArgs {
     const BatchDesc *batch;  // batched launches: per-solve descriptors
     const int *tile_req;     // batched launches: solve index of every tile
     int parity;              // batched launches: stage count since cur0, mod 2
+    // FP64 field path: fields, residual and operators in FP64 (factors in
+    // geo64 / fgeo64), RK coefficients and flux parameter in FP64
+    const double *qin64;
+    double *qout64;
+    double *res64;
+    const double *ops64;       // row-major Dr, Ds, LIFT (scalar-operand kernel)
+    const double *opsfrag64;   // A-fragment order (FP64 matrix-core kernel)
+    double a64, b64, dt64, alpha64;
     int Kp;
     int ntiles;
     int ngroups;  // work-groups of a persistent launch (multiple of 8)
@@ -91,6 +99,17 @@ int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const
 int blocks_per_cu_2d_mfma(int N, bool material);
 int blocks_per_cu_3d(int N);
 
+// FP64 2D stage on FP64 fields (a.qin64 / a.qout64 / a.res64, a.geo64 /
+// a.fgeo64, a.a64 / a.b64 / a.dt64 / a.alpha64): the scalar-operand kernel
+// (row-major a.ops64) or the matrix-core kernel (a.opsfrag64, persistent
+// grid of a.ngroups work-groups)
+hipError_t launch_stage2d_fp64(int N, bool material, const StageArgs &a, hipStream_t s);
+hipError_t launch_stage2d_f64(int N, bool material, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_2d_f64(int N, bool material);
+// fragment-ordered FP64 Dr, Ds, LIFT of the matrix-core kernel; with
+// out == nullptr returns the required length
+int opsfrag2d_f64(int N, const double *Dr, const double *Ds, const double *LIFT, double *out);
+
 // Split-precision 2D stage (prec 1 = BF16 hi+lo, 2 = FP16 hi+lo), FP32
 // accumulation, FP64 geometric factors (geo64 / fgeo64).
 hipError_t launch_stage2d_split(int N, bool material, int prec, const StageArgs &a, hipStream_t s);
@@ -108,6 +127,7 @@ int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt,
 // into partial[nblocks].
 struct ReduceArgs {
     const float *q;
+    const double *q64;    // FP64 fields (FP64 solvers; q unused then)
     const double *J;      // [Kp]
     const double *Mref;   // [Np][Np]
     const double *w;      // [n_fields][Kp] or nullptr
@@ -120,6 +140,7 @@ hipError_t launch_energy(const ReduceArgs &a, int nblocks, hipStream_t stream);
 // error mass norm squared, partial[2*b+1] the reference's.
 struct CavityArgs {
     float *q;             // fields (written by init, read by error)
+    double *q64;          // FP64 fields instead (FP64 solvers)
     const double *x, *y, *z;   // node coordinates [Np][Kp]
     const double *J;
     const double *Mref;

@@ -53,9 +53,14 @@ int64_t solver_footprint(int dim, int order, int64_t K, bool material, int prec)
     const int64_t Nf = dim + 1, nf = dim == 2 ? 3 : 6;
     const int64_t G = dim == 2 ? (material ? 6 : 4) : 9, FG = dim == 2 ? (material ? 6 : 3) : 4;
     const int64_t Kp = (K + kTile - 1) / kTile * kTile;
-    int64_t b = 3 * nf * Np * Kp * 4;                    // q ping-pong and res
+    const int64_t wq = prec == DGW_FP64 ? 8 : 4;        // bytes per field value
+    int64_t b = 3 * nf * Np * Kp * wq;                   // q ping-pong and res
     b += (G + Nf * FG) * Kp * 4 + Nf * Kp * 4;          // factors and face records
     if (prec != DGW_FP32) b += (G + Nf * FG) * Kp * 8;  // FP64 factors
+    if (prec == DGW_FP64) {  // FP64 operators, row-major and in fragment order
+        const int64_t MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nf * Nfp + 3) / 4;
+        b += Np * (dim * Np + Nf * Nfp) * 8 + (2 * MT * KV + MT * KL) * 64 * 8;
+    }
     b += Kp * 4 + Kp * 8 + dim * Np * Kp * 8;           // permutation, J, node coordinates
     if (material) b += nf * Kp * 8;                     // energy weights
     b += 4 * Np * (dim * Np + Nf * Nfp) * 4 + Np * Np * 8 + 64 * 1024;  // operators, tables, scratch
@@ -100,7 +105,7 @@ void free_device(dgw_solver *s) {
     hipSetDevice(s->opts.device);
     void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->opsfrag_d, s->nbr_d, s->itab_d, s->perm_d,
                     s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d,
-                    s->geo64_d, s->fgeo64_d};
+                    s->geo64_d, s->fgeo64_d, s->q64[0], s->q64[1], s->res64, s->ops64_d, s->opsfrag64_d};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (s->ev0) hipEventDestroy(s->ev0);
@@ -126,11 +131,19 @@ int setup_device(dgw_solver *s) {
     DGW_HIP(hipEventCreate(&s->ev1));
     const size_t nstate = (size_t)nf * Np * Kp;
     int rc;
-    if ((rc = dalloc(&s->q[0], nstate)) || (rc = dalloc(&s->q[1], nstate)) || (rc = dalloc(&s->res, nstate)))
-        return rc;
-    DGW_HIP(hipMemset(s->q[0], 0, nstate * sizeof(float)));
-    DGW_HIP(hipMemset(s->q[1], 0, nstate * sizeof(float)));
-    DGW_HIP(hipMemset(s->res, 0, nstate * sizeof(float)));
+    if (s->fp64) {
+        if ((rc = dalloc(&s->q64[0], nstate)) || (rc = dalloc(&s->q64[1], nstate)) || (rc = dalloc(&s->res64, nstate)))
+            return rc;
+        DGW_HIP(hipMemset(s->q64[0], 0, nstate * sizeof(double)));
+        DGW_HIP(hipMemset(s->q64[1], 0, nstate * sizeof(double)));
+        DGW_HIP(hipMemset(s->res64, 0, nstate * sizeof(double)));
+    } else {
+        if ((rc = dalloc(&s->q[0], nstate)) || (rc = dalloc(&s->q[1], nstate)) || (rc = dalloc(&s->res, nstate)))
+            return rc;
+        DGW_HIP(hipMemset(s->q[0], 0, nstate * sizeof(float)));
+        DGW_HIP(hipMemset(s->q[1], 0, nstate * sizeof(float)));
+        DGW_HIP(hipMemset(s->res, 0, nstate * sizeof(float)));
+    }
 
     // per-element factors
     std::vector<double> geo((size_t)s->G * Kp, 0.0);
@@ -189,8 +202,10 @@ int setup_device(dgw_solver *s) {
     }
     // operators and tables
     std::vector<float> ops;
+    std::vector<double> ops64;
     auto put = [&](const dgw::Mat &M) {
         for (double v : M.a) ops.push_back((float)v);
+        ops64.insert(ops64.end(), M.a.begin(), M.a.end());
     };
     put(R.Dr);
     put(R.Ds);
@@ -201,9 +216,16 @@ int setup_device(dgw_solver *s) {
         for (int o = 0; o < R.n_orient; ++o)
             for (int i = 0; i < Nfp; ++i) itab.push_back(R.face_nodes[f2 * Nfp + R.orient_perm[o * Nfp + i]]);
     std::vector<int> permv(s->perm.begin(), s->perm.end());
-    const bool split = s->opts.prec != DGW_FP32;
+    const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
+    const bool need64 = s->opts.prec != DGW_FP32;  // FP64 factors on the device
     std::vector<float> opsfrag;
-    if (split && dim == 3) {
+    std::vector<double> opsfrag64;
+    if (s->fp64) {
+        // FP64 fragments of the matrix-core kernel (the scalar-operand kernel
+        // reads the row-major FP64 operators)
+        opsfrag64.resize(dgw::opsfrag2d_f64(s->N, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag2d_f64(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag64.data());
+    } else if (split && dim == 3) {
         const int bytes = dgw::opsfrag3d_split(s->N, nullptr, nullptr, nullptr, nullptr, nullptr);
         opsfrag.resize(bytes / sizeof(float));
         dgw::opsfrag3d_split(s->N, R.Dr.a.data(), R.Ds.a.data(), R.Dt.a.data(), R.LIFT.a.data(), opsfrag.data());
@@ -241,10 +263,11 @@ int setup_device(dgw_solver *s) {
     {
         int ncu = 0;
         DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-        const int per_cu = split ? (dim == 2 ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
-                                             : dgw::blocks_per_cu_3d_split(s->N))
-                                 : (dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
-                                             : dgw::blocks_per_cu_3d(s->N));
+        const int per_cu = s->fp64 ? dgw::blocks_per_cu_2d_f64(s->N, s->material)
+                           : split ? (dim == 2 ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
+                                               : dgw::blocks_per_cu_3d_split(s->N))
+                                   : (dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
+                                               : dgw::blocks_per_cu_3d(s->N));
         const int ntiles = (int)(Kp / dgw::kTile);
         int ng = std::max(1, ncu) * per_cu;
         ng = std::min(ng, (ntiles + 7) / 8 * 8);
@@ -253,8 +276,11 @@ int setup_device(dgw_solver *s) {
     if (dim == 3 && (rc = dalloc(&s->z_d, Z.size()))) return rc;
     if (s->material && (rc = dalloc(&s->w_d, w.size()))) return rc;
     std::vector<float> geo32(geo.begin(), geo.end()), fgeo32(fgeo.begin(), fgeo.end());
-    if (split && ((rc = dalloc(&s->geo64_d, geo.size())) || (rc = dalloc(&s->fgeo64_d, fgeo.size())) ||
-                  (rc = upload(s->geo64_d, geo)) || (rc = upload(s->fgeo64_d, fgeo))))
+    if (need64 && ((rc = dalloc(&s->geo64_d, geo.size())) || (rc = dalloc(&s->fgeo64_d, fgeo.size())) ||
+                   (rc = upload(s->geo64_d, geo)) || (rc = upload(s->fgeo64_d, fgeo))))
+        return rc;
+    if (s->fp64 && ((rc = dalloc(&s->ops64_d, ops64.size())) || (rc = upload(s->ops64_d, ops64)) ||
+                    (rc = dalloc(&s->opsfrag64_d, opsfrag64.size())) || (rc = upload(s->opsfrag64_d, opsfrag64))))
         return rc;
     if ((rc = upload(s->geo_d, geo32)) || (rc = upload(s->fgeo_d, fgeo32)) || (rc = upload(s->nbr_d, nbr)) ||
         (rc = upload(s->ops_d, ops)) || (rc = upload(s->itab_d, itab)) || (rc = upload(s->perm_d, permv)) ||
@@ -287,10 +313,31 @@ dgw::StageArgs stage_args(const dgw_solver *s) {
     a.ntiles = (int)(s->Kp / dgw::kTile);
     a.ngroups = s->ngroups;
     a.alpha = (float)s->opts.alpha;
+    a.res64 = s->res64;
+    a.ops64 = s->ops64_d;
+    a.opsfrag64 = s->opsfrag64_d;
+    a.alpha64 = s->opts.alpha;
     return a;
 }
 
+// stage input / output buffers and RK coefficients of one launch
+void set_stage(const dgw_solver *s, dgw::StageArgs &a, double ca, double cb, double dt) {
+    a.qin = s->q[s->cur];
+    a.qout = s->q[1 - s->cur];
+    a.qin64 = s->q64[s->cur];
+    a.qout64 = s->q64[1 - s->cur];
+    a.a = (float)ca;
+    a.b = (float)cb;
+    a.dt = (float)dt;
+    a.a64 = ca;
+    a.b64 = cb;
+    a.dt64 = dt;
+}
+
 hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t st) {
+    if (s->fp64)
+        return s->opts.kernel == dgw::kVariantScalarOperand ? dgw::launch_stage2d_fp64(s->N, s->material, a, st)
+                                                            : dgw::launch_stage2d_f64(s->N, s->material, a, st);
     if (s->opts.prec != DGW_FP32)
         return s->dim == 2 ? dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st)
                            : dgw::launch_stage3d_split(s->N, a, st);
@@ -299,40 +346,53 @@ hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t 
 
 int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) {
     dgw::StageArgs a = stage_args(s);
-    a.dt = (float)dt;
     for (int64_t n = 0; n < nsteps; ++n)
         for (int st5 = 0; st5 < 5; ++st5) {
-            a.qin = s->q[s->cur];
-            a.qout = s->q[1 - s->cur];
-            a.a = (float)kRkA[st5];
-            a.b = (float)kRkB[st5];
+            set_stage(s, a, kRkA[st5], kRkB[st5], dt);
             DGW_HIP(launch_one(s, a, st));
             s->cur = 1 - s->cur;
         }
     return DGW_OK;
 }
 
-// caller-order FP64 [nf][K][Np] -> internal FP32 node-major upload into q[cur]
-int upload_fields(dgw_solver *s, const double *q) {
+// caller-order FP64 [nf][K][Np] -> internal node-major upload (in the
+// solver's field type T) into dst
+template <typename T>
+int upload_fields_t(dgw_solver *s, const double *q, T *dst) {
     const int Np = s->Np, nf = s->nf;
     const int64_t K = s->K, Kp = s->Kp;
-    std::vector<float> h((size_t)nf * Np * Kp, 0.0f);
+    std::vector<T> h((size_t)nf * Np * Kp, T(0));
     for (int f = 0; f < nf; ++f)
         for (int64_t e = 0; e < K; ++e) {
             const int64_t k = s->perm[e];
             const double *src = q + ((size_t)f * K + k) * Np;
-            for (int n = 0; n < Np; ++n) h[dgw::tix(e, f * Np + n, nf * Np)] = (float)src[n];
+            for (int n = 0; n < Np; ++n) h[dgw::tix(e, f * Np + n, nf * Np)] = (T)src[n];
         }
-    DGW_HIP(hipMemcpy(s->q[s->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    DGW_HIP(hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
     return DGW_OK;
 }
 
-int download(dgw_solver *s, const float *src_d, double *out) {
+int upload_fields(dgw_solver *s, const double *q) {
+    return s->fp64 ? upload_fields_t(s, q, s->q64[s->cur]) : upload_fields_t(s, q, s->q[s->cur]);
+}
+
+// zero the RK residual (asynchronously on st)
+int clear_res(dgw_solver *s, hipStream_t st) {
+    const size_t n = (size_t)s->nf * s->Np * s->Kp;
+    if (s->fp64)
+        DGW_HIP(hipMemsetAsync(s->res64, 0, n * sizeof(double), st));
+    else
+        DGW_HIP(hipMemsetAsync(s->res, 0, n * sizeof(float), st));
+    return DGW_OK;
+}
+
+template <typename T>
+int download(dgw_solver *s, const T *src_d, double *out) {
     const int Np = s->Np, nf = s->nf;
     const int64_t K = s->K, Kp = s->Kp;
-    std::vector<float> h((size_t)nf * Np * Kp);
+    std::vector<T> h((size_t)nf * Np * Kp);
     DGW_HIP(hipStreamSynchronize(s->stream));
-    DGW_HIP(hipMemcpy(h.data(), src_d, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+    DGW_HIP(hipMemcpy(h.data(), src_d, h.size() * sizeof(T), hipMemcpyDeviceToHost));
     for (int f = 0; f < nf; ++f)
         for (int64_t e = 0; e < K; ++e) {
             const int64_t k = s->perm[e];
@@ -429,17 +489,18 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (opts_in) opts = *opts_in;
     if (opts.cfl <= 0) opts.cfl = 1.0;
     if (!(opts.alpha >= 0.0 && opts.alpha <= 1.0)) return fail(DGW_EINVAL, "alpha must be in [0, 1]");
-    if (opts.prec != DGW_FP32 && opts.prec != DGW_SPLIT_BF16 && opts.prec != DGW_SPLIT_FP16)
+    if (opts.prec != DGW_FP32 && opts.prec != DGW_SPLIT_BF16 && opts.prec != DGW_SPLIT_FP16 && opts.prec != DGW_FP64)
         return fail(DGW_EINVAL, "unknown precision variant");
-    if (opts.prec == DGW_SPLIT_FP16 && mesh->dim != 2)
+    if ((opts.prec == DGW_SPLIT_FP16 || opts.prec == DGW_FP64) && mesh->dim != 2)
         return fail(DGW_EINVAL, "the 3D path has the FP32 and split-BF16 variants");
     if (opts.kernel < 0 || opts.kernel > 2) return fail(DGW_EINVAL, "kernel variant must be 0, 1 or 2");
-    if (opts.prec != DGW_FP32 && opts.kernel == 1)
+    if ((opts.prec == DGW_SPLIT_BF16 || opts.prec == DGW_SPLIT_FP16) && opts.kernel == 1)
         return fail(DGW_EINVAL, "split-precision variants run on the matrix cores only (kernel 0 or 2)");
     auto t0 = std::chrono::steady_clock::now();
     dgw_solver *s = new (std::nothrow) dgw_solver();
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
     s->opts = opts;
+    s->fp64 = opts.prec == DGW_FP64;
     s->dim = mesh->dim;
     s->N = order;
     try {
@@ -532,8 +593,8 @@ int dgw_set_fields(dgw_solver *s, const double *q) {
     if (!q) return fail(DGW_EINVAL, "NULL fields");
     DGW_HIP(hipSetDevice(s->opts.device));
     DGW_HIP(hipStreamSynchronize(s->stream));
-    if ((rc = upload_fields(s, q))) return rc;
-    DGW_HIP(hipMemset(s->res, 0, (size_t)s->nf * s->Np * s->Kp * sizeof(float)));
+    if ((rc = upload_fields(s, q)) || (rc = clear_res(s, s->stream))) return rc;
+    DGW_HIP(hipStreamSynchronize(s->stream));
     s->t = 0.0;
     return DGW_OK;
 }
@@ -543,7 +604,7 @@ int dgw_get_fields(dgw_solver *s, double *q) {
     if (rc) return rc;
     if (!q) return fail(DGW_EINVAL, "NULL fields");
     DGW_HIP(hipSetDevice(s->opts.device));
-    return download(s, s->q[s->cur], q);
+    return s->fp64 ? download(s, s->q64[s->cur], q) : download(s, s->q[s->cur], q);
 }
 
 int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]) {
@@ -553,6 +614,7 @@ int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]) {
     DGW_HIP(hipSetDevice(s->opts.device));
     dgw::CavityArgs a{};
     a.q = s->q[s->cur];
+    a.q64 = s->q64[s->cur];
     a.x = s->x_d;
     a.y = s->y_d;
     a.z = s->z_d;
@@ -567,7 +629,7 @@ int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]) {
     a.mu = s->g.mu[0];
     a.t = 0.0;
     DGW_HIP(dgw::launch_cavity_init(a, s->stream));
-    DGW_HIP(hipMemsetAsync(s->res, 0, (size_t)s->nf * s->Np * s->Kp * sizeof(float), s->stream));
+    if ((rc = clear_res(s, s->stream))) return rc;
     DGW_HIP(hipStreamSynchronize(s->stream));
     s->t = 0.0;
     return DGW_OK;
@@ -616,14 +678,10 @@ int dgw_rhs(dgw_solver *s, const double *q, double *rhs) {
     if (!q || !rhs) return fail(DGW_EINVAL, "NULL argument");
     if ((rc = dgw_set_fields(s, q))) return rc;
     dgw::StageArgs a = stage_args(s);
-    a.qin = s->q[s->cur];
-    a.qout = s->q[1 - s->cur];
-    a.a = 0.0f;
-    a.b = 0.0f;
-    a.dt = 1.0f;
+    set_stage(s, a, 0.0, 0.0, 1.0);
     DGW_HIP(launch_one(s, a, s->stream));
     s->cur = 1 - s->cur;
-    return download(s, s->res, rhs);
+    return s->fp64 ? download(s, s->res64, rhs) : download(s, s->res, rhs);
 }
 
 int dgw_energy(dgw_solver *s, double *energy) {
@@ -633,6 +691,7 @@ int dgw_energy(dgw_solver *s, double *energy) {
     DGW_HIP(hipSetDevice(s->opts.device));
     dgw::ReduceArgs a{};
     a.q = s->q[s->cur];
+    a.q64 = s->q64[s->cur];
     a.J = s->J_d;
     a.Mref = s->M_d;
     a.w = s->w_d;
@@ -659,6 +718,7 @@ int dgw_cavity_error(dgw_solver *s, const int32_t mode[3], double t, double *rel
     DGW_HIP(hipSetDevice(s->opts.device));
     dgw::CavityArgs a{};
     a.q = s->q[s->cur];
+    a.q64 = s->q64[s->cur];
     a.x = s->x_d;
     a.y = s->y_d;
     a.z = s->z_d;
@@ -699,10 +759,11 @@ int dgw_set_fields_dev(dgw_solver *s, const float *q_dev, void *stream) {
     int rc = need_device(s);
     if (rc) return rc;
     if (!q_dev) return fail(DGW_EINVAL, "NULL fields");
+    if (s->fp64) return fail(DGW_EINVAL, "FP32 device fields given to an FP64 solver");
     hipStream_t st = stream ? (hipStream_t)stream : s->stream;
     DGW_HIP(hipSetDevice(s->opts.device));
     DGW_HIP(dgw::launch_to_internal(q_dev, s->q[s->cur], s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf, st));
-    DGW_HIP(hipMemsetAsync(s->res, 0, (size_t)s->nf * s->Np * s->Kp * sizeof(float), st));
+    if ((rc = clear_res(s, st))) return rc;
     s->t = 0.0;
     return DGW_OK;
 }
@@ -711,6 +772,7 @@ int dgw_get_fields_dev(dgw_solver *s, float *q_dev, void *stream) {
     int rc = need_device(s);
     if (rc) return rc;
     if (!q_dev) return fail(DGW_EINVAL, "NULL fields");
+    if (s->fp64) return fail(DGW_EINVAL, "FP32 device fields requested from an FP64 solver");
     hipStream_t st = stream ? (hipStream_t)stream : s->stream;
     DGW_HIP(hipSetDevice(s->opts.device));
     DGW_HIP(dgw::launch_to_caller(s->q[s->cur], q_dev, s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf, st));
@@ -732,10 +794,12 @@ int dgw_stage_cost(const dgw_solver *s, double *bytes, double *flops) {
     if (!s) return fail(DGW_EINVAL, "NULL solver");
     const int Nafp = s->Nfaces * s->Nfp;
     // algorithmic HBM traffic per element: read q_in and res, write res and
-    // q_out (4 words per DOF) plus the per-element and per-face factors (FP32,
-    // or FP64 in the split-precision variants) and the face records
+    // q_out (4 words per DOF, FP32 or FP64) plus the per-element and per-face
+    // factors (FP32, or FP64 in the split-precision and FP64 variants) and
+    // the face records
     const double wg = s->opts.prec == DGW_FP32 ? 4.0 : 8.0;
-    const double per_el = 16.0 * s->nf * s->Np + wg * s->G + s->Nfaces * (wg * s->FG + 4.0);
+    const double wq = s->fp64 ? 8.0 : 4.0;
+    const double per_el = 4.0 * wq * s->nf * s->Np + wg * s->G + s->Nfaces * (wg * s->FG + 4.0);
     if (bytes) *bytes = per_el * double(s->K);
     if (flops) *flops = flops_per_element(s->dim, s->Np, Nafp, s->nf) * double(s->K);
     return DGW_OK;

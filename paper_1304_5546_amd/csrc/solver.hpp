@@ -27,11 +27,14 @@ struct dgw_solver {
     bool on_device = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool fp64 = false;  // DGW_FP64: fields in q64 / res64, FP32 q / res unused
     float *q[2] = {nullptr, nullptr};
     float *res = nullptr;
+    double *q64[2] = {nullptr, nullptr};
+    double *res64 = nullptr, *ops64_d = nullptr, *opsfrag64_d = nullptr;
     int cur = 0;
     float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr, *opsfrag_d = nullptr;
-    double *geo64_d = nullptr, *fgeo64_d = nullptr;  // split-precision variants only
+    double *geo64_d = nullptr, *fgeo64_d = nullptr;  // split-precision and FP64 variants only
     int *nbr_d = nullptr, *itab_d = nullptr, *perm_d = nullptr;
     double *J_d = nullptr, *M_d = nullptr, *w_d = nullptr, *x_d = nullptr, *y_d = nullptr, *z_d = nullptr;
     double *partial_d = nullptr;

@@ -1,4 +1,6 @@
-// Fused LSRK stage for 2D TM Maxwell on triangles, FP32, gfx950.
+// Fused LSRK stage for 2D TM Maxwell on triangles, gfx950, on FP32 fields
+// (a cross-check of the MFMA kernel) or FP64 fields (the double-precision
+// path: fields, residual, operators, factors and arithmetic all FP64).
 //
 // One work-group (4 waves) owns a tile of 64 consecutive elements; lane l of
 // every wave works on element tile*64 + l, so every global access to the
@@ -32,18 +34,36 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + (x < r ? x : r) + i;
 }
 
-template <int N, bool MAT>
-__global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
+// The solve's buffers and coefficients in the arithmetic type R.
+template <typename R>
+struct Bufs {
+    const R *qin;
+    R *qout, *res;
+    const R *geo, *fgeo, *ops;
+    R a, b, dt, alpha;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ Bufs<R> bufs(const StageArgs &A) {
+    if constexpr (sizeof(R) == 8)
+        return Bufs<R>{A.qin64, A.qout64, A.res64, A.geo64, A.fgeo64, A.ops64, A.a64, A.b64, A.dt64, A.alpha64};
+    else
+        return Bufs<R>{A.qin, A.qout, A.res, A.geo, A.fgeo, A.ops, A.a, A.b, A.dt, A.alpha};
+}
+
+template <typename R, int N, bool MAT>
+__global__ void __launch_bounds__(256) stage2d_kernel(StageArgs SA) {
+    const Bufs<R> A = bufs<R>(SA);
     constexpr int Np = (N + 1) * (N + 2) / 2;
     constexpr int Nfp = N + 1;
     constexpr int Nafp = 3 * Nfp;
     constexpr int NW = 4;
-    constexpr int R = (Np + NW - 1) / NW;
+    constexpr int NR = (Np + NW - 1) / NW;  // output nodes per wave
     constexpr int FG = MAT ? 6 : 3;
     constexpr int TE = kTile;
 
-    __shared__ float sq[3 * Np * TE];
-    __shared__ float sf[3 * Nafp * TE];
+    __shared__ R sq[3 * Np * TE];
+    __shared__ R sf[3 * Nafp * TE];
     __shared__ int stab[3 * 2 * Nfp];
 
     const int lane = threadIdx.x & 63;
@@ -51,14 +71,14 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int e = tile * TE + lane;
 
-    for (int i = threadIdx.x; i < 3 * 2 * Nfp; i += 256) stab[i] = A.itab[Nafp + i];
+    for (int i = threadIdx.x; i < 3 * 2 * Nfp; i += 256) stab[i] = SA.itab[Nafp + i];
 
     // 1. fields of the tile into LDS; prefetch this wave's residual entries
 #pragma unroll
     for (int row = w; row < 3 * Np; row += NW) sq[row * TE + lane] = A.qin[tix(e, row, 3 * Np)];
-    float rres[3][R];
+    R rres[3][NR];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
 #pragma unroll
         for (int f = 0; f < 3; ++f) rres[f][r] = A.res[tix(e, f * Np + n, 3 * Np)];
@@ -69,12 +89,12 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
 #pragma unroll
     for (int j = w; j < Nafp; j += NW) {
         const int face = j / Nfp, i = j - face * Nfp;
-        const int own = A.itab[j];
-        const float mHx = sq[(0 * Np + own) * TE + lane];
-        const float mHy = sq[(1 * Np + own) * TE + lane];
-        const float mEz = sq[(2 * Np + own) * TE + lane];
-        const int rec = A.nbr[tix(e, face, 3)];
-        float pHx, pHy, pEz;
+        const int own = SA.itab[j];
+        const R mHx = sq[(0 * Np + own) * TE + lane];
+        const R mHy = sq[(1 * Np + own) * TE + lane];
+        const R mEz = sq[(2 * Np + own) * TE + lane];
+        const int rec = SA.nbr[tix(e, face, 3)];
+        R pHx, pHy, pEz;
         if (rec < 0) {  // PEC wall: mirror state E+ = -E-, H+ = H-
             pHx = mHx;
             pHy = mHy;
@@ -86,25 +106,25 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
             pHy = A.qin[tix(e2, 1 * Np + pn, 3 * Np)];
             pEz = A.qin[tix(e2, 2 * Np + pn, 3 * Np)];
         }
-        const float *fg = A.fgeo + tix(e, face * FG, 3 * FG);  // rows face*FG + q are 64 apart
-        const float nx = fg[0], ny = fg[64];
-        const float dHx = mHx - pHx, dHy = mHy - pHy, dEz = mEz - pEz;
-        const float dh = nx * dHy - ny * dHx;  // jump of the tangential field
-        float cEE, cEh, cHE, cHh;
+        const R *fg = A.fgeo + tix(e, face * FG, 3 * FG);  // rows face*FG + q are 64 apart
+        const R nx = fg[0], ny = fg[64];
+        const R dHx = mHx - pHx, dHy = mHy - pHy, dEz = mEz - pEz;
+        const R dh = nx * dHy - ny * dHx;  // jump of the tangential field
+        R cEE, cEh, cHE, cHh;
         if (MAT) {
             cEE = fg[2 * 64];
             cEh = fg[3 * 64];
             cHE = fg[4 * 64];
             cHh = fg[5 * 64];
         } else {
-            const float hs = 0.5f * fg[2 * 64];
+            const R hs = R(0.5) * fg[2 * 64];
             cEE = A.alpha * hs;
             cEh = hs;
             cHE = hs;
             cHh = A.alpha * hs;
         }
-        const float fE = -(cEE * dEz + cEh * dh);
-        const float fH = cHE * dEz + cHh * dh;
+        const R fE = -(cEE * dEz + cEh * dh);
+        const R fH = cHE * dEz + cHh * dh;
         sf[(0 * Nafp + j) * TE + lane] = ny * fH;
         sf[(1 * Nafp + j) * TE + lane] = -nx * fH;
         sf[(2 * Nafp + j) * TE + lane] = fE;
@@ -112,23 +132,23 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
     __syncthreads();
 
     // 3. local differentiation of the three fields for this wave's nodes
-    const float *Dr = A.ops;
-    const float *Ds = A.ops + Np * Np;
-    const float *L = A.ops + 2 * Np * Np;
-    float ar[3][R], as[3][R];
+    const R *Dr = A.ops;
+    const R *Ds = A.ops + Np * Np;
+    const R *L = A.ops + 2 * Np * Np;
+    R ar[3][NR], as[3][NR];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int f = 0; f < 3; ++f) ar[f][r] = as[f][r] = 0.f;
+        for (int f = 0; f < 3; ++f) ar[f][r] = as[f][r] = R(0);
 #pragma unroll
     for (int jn = 0; jn < Np; ++jn) {
-        const float v0 = sq[(0 * Np + jn) * TE + lane];
-        const float v1 = sq[(1 * Np + jn) * TE + lane];
-        const float v2 = sq[(2 * Np + jn) * TE + lane];
+        const R v0 = sq[(0 * Np + jn) * TE + lane];
+        const R v1 = sq[(1 * Np + jn) * TE + lane];
+        const R v2 = sq[(2 * Np + jn) * TE + lane];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
-            const float cr = Dr[n * Np + jn], cs = Ds[n * Np + jn];
+            const R cr = Dr[n * Np + jn], cs = Ds[n * Np + jn];
             ar[0][r] += cr * v0;
             as[0][r] += cs * v0;
             ar[1][r] += cr * v1;
@@ -138,19 +158,19 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
         }
     }
     constexpr int G = MAT ? 6 : 4;
-    const float rx = A.geo[tix(e, 0, G)], ry = A.geo[tix(e, 1, G)];
-    const float sx = A.geo[tix(e, 2, G)], sy = A.geo[tix(e, 3, G)];
-    float rhs[3][R];
+    const R rx = A.geo[tix(e, 0, G)], ry = A.geo[tix(e, 1, G)];
+    const R sx = A.geo[tix(e, 2, G)], sy = A.geo[tix(e, 3, G)];
+    R rhs[3][NR];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < NR; ++r) {
         rhs[0][r] = -(ry * ar[2][r] + sy * as[2][r]);
         rhs[1][r] = rx * ar[2][r] + sx * as[2][r];
         rhs[2][r] = (rx * ar[1][r] + sx * as[1][r]) - (ry * ar[0][r] + sy * as[0][r]);
     }
     if (MAT) {
-        const float ieps = A.geo[tix(e, 4, G)], imu = A.geo[tix(e, 5, G)];
+        const R ieps = A.geo[tix(e, 4, G)], imu = A.geo[tix(e, 5, G)];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < NR; ++r) {
             rhs[0][r] *= imu;
             rhs[1][r] *= imu;
             rhs[2][r] *= ieps;
@@ -160,13 +180,13 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
     // 4. LIFT apply
 #pragma unroll
     for (int j = 0; j < Nafp; ++j) {
-        const float f0 = sf[(0 * Nafp + j) * TE + lane];
-        const float f1 = sf[(1 * Nafp + j) * TE + lane];
-        const float f2 = sf[(2 * Nafp + j) * TE + lane];
+        const R f0 = sf[(0 * Nafp + j) * TE + lane];
+        const R f1 = sf[(1 * Nafp + j) * TE + lane];
+        const R f2 = sf[(2 * Nafp + j) * TE + lane];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int n = (w + NW * r < Np) ? w + NW * r : Np - 1;
-            const float c = L[n * Nafp + j];
+            const R c = L[n * Nafp + j];
             rhs[0][r] += c * f0;
             rhs[1][r] += c * f1;
             rhs[2][r] += c * f2;
@@ -175,13 +195,13 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
 
     // 5. fused low-storage RK update
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int n = w + NW * r;
         if (n < Np) {
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 const size_t idx = tix(e, f * Np + n, 3 * Np);
-                const float rr = A.a * rres[f][r] + A.dt * rhs[f][r];
+                const R rr = A.a * rres[f][r] + A.dt * rhs[f][r];
                 A.res[idx] = rr;
                 A.qout[idx] = sq[(f * Np + n) * TE + lane] + A.b * rr;
             }
@@ -189,9 +209,12 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs A) {
     }
 }
 
-template <int N, bool MAT>
+template <typename R, int N, bool MAT>
 static hipError_t launch2d(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((stage2d_kernel<N, MAT>), dim3(a.ntiles), dim3(256), 0, s, a);
+    const Bufs<R> b = bufs<R>(a);
+    if (a.ntiles <= 0 || !b.qin || !b.qout || !b.res || !b.geo || !b.fgeo || !b.ops || !a.nbr || !a.itab)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((stage2d_kernel<R, N, MAT>), dim3(a.ntiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -203,7 +226,26 @@ hipError_t launch_stage(int dim, int N, bool material, int variant, const StageA
     if (variant != kVariantScalarOperand) return launch_stage2d_mfma(N, material, a, s);
 #define DGW_CASE(n)                                                    \
     case n:                                                            \
-        return material ? launch2d<n, true>(a, s) : launch2d<n, false>(a, s);
+        return material ? launch2d<float, n, true>(a, s) : launch2d<float, n, false>(a, s);
+    switch (N) {
+        DGW_CASE(1)
+        DGW_CASE(2)
+        DGW_CASE(3)
+        DGW_CASE(4)
+        DGW_CASE(5)
+        DGW_CASE(6)
+        DGW_CASE(7)
+        DGW_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef DGW_CASE
+}
+
+hipError_t launch_stage2d_fp64(int N, bool material, const StageArgs &a, hipStream_t s) {
+#define DGW_CASE(n)                                                    \
+    case n:                                                            \
+        return material ? launch2d<double, n, true>(a, s) : launch2d<double, n, false>(a, s);
     switch (N) {
         DGW_CASE(1)
         DGW_CASE(2)
@@ -223,7 +265,7 @@ const char *stage_kernel_name(int dim, int N, bool material, int variant) {
     (void)N;
     if (dim == 3) return stage3d_kernel_name(N);
     if (variant != kVariantScalarOperand) return material ? "stage2d_mfma_kernel<N, true, false>" : "stage2d_mfma_kernel<N, false, false>";
-    return material ? "stage2d_kernel<N, true>" : "stage2d_kernel<N, false>";
+    return material ? "stage2d_kernel<float, N, true>" : "stage2d_kernel<float, N, false>";
 }
 
 }  // namespace dgw

@@ -18,8 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgw.so")
 
-DGW_FP32, DGW_SPLIT_BF16, DGW_SPLIT_FP16 = 0, 1, 2
-PRECISIONS = {"fp32": DGW_FP32, "split_bf16": DGW_SPLIT_BF16, "split_fp16": DGW_SPLIT_FP16}
+DGW_FP32, DGW_SPLIT_BF16, DGW_SPLIT_FP16, DGW_FP64 = 0, 1, 2, 3
+PRECISIONS = {"fp32": DGW_FP32, "split_bf16": DGW_SPLIT_BF16, "split_fp16": DGW_SPLIT_FP16, "fp64": DGW_FP64}
 
 ERRORS = {0: "DGW_OK", -1: "DGW_EINVAL", -2: "DGW_EMESH", -3: "DGW_EORDER", -4: "DGW_ENOMEM",
           -5: "DGW_ETOOBIG", -6: "DGW_EDEVICE", -7: "DGW_ENONFINITE", -8: "DGW_ECANCELLED",

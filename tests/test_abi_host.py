@@ -142,6 +142,9 @@ def test_error_paths_before_any_device_call():
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="split_fp16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec="split_fp16", kernel=1, device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec=7, device=-1))
+    # the FP64 field path is 2D only
+    _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="fp64", device=-1))
+    dgw.Solver(m, 3, prec="fp64", kernel=1, device=-1).close()
     # NULL arguments at the raw ABI
     L = dgw.lib()
     h = C.c_void_p()
@@ -162,4 +165,7 @@ def test_footprint_is_host_only_and_scales():
     mat.eps = np.full(mat.K, 2.25)
     assert dgw.footprint(mat, 5) > f5  # material factors and energy weights
     assert dgw.footprint(m, 5, prec="split_bf16") > f5  # FP64 factors
+    # FP64 fields: twice the state bytes, FP64 factors and operators on top
+    f64 = dgw.footprint(m, 5, prec="fp64")
+    assert f64 - dgw.footprint(m, 5, prec="split_bf16") > 3 * 3 * 21 * Kp * 4
     _expect("DGW_EORDER", lambda: dgw.footprint(m, 9))
