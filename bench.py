@@ -166,7 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--kernel", type=int, default=0, help="stage kernel: 0 auto, 1 scalar-operand VALU, 2 MFMA")
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-operand MFMA, 3 derivative-first MFMA")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "split_bf16", "split_fp16", "fp64"],
                     help="arithmetic of the timed path (value and roofline)")
     ap.add_argument("--serve", action="store_true", help="run the serving configuration instead")
@@ -249,11 +250,12 @@ def main():
     if dim == 3:
         kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
     elif pcode == 3:
-        kname = f"stage2d_kernel<double, {N}, false>" if args.kernel == 1 else f"stage2d_f64_kernel<{N}, false>"
+        kname = f"stage2d_kernel<double, {N}, false>" if args.kernel == 1 else f"stage2d_df_kernel<double, {N}, false>"
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
-        kname = f"stage2d_kernel<float, {N}, false>" if args.kernel == 1 else f"stage2d_mfma_kernel<{N}, false, false>"
+        kname = {1: f"stage2d_kernel<float, {N}, false>",
+                 3: f"stage2d_df_kernel<float, {N}, false>"}.get(args.kernel, f"stage2d_mfma_kernel<{N}, false, false>")
     out = {
         "metric": METRIC,
         "value": value,

@@ -85,11 +85,12 @@ typedef struct {
  * The split variants evaluate each Op*B product (Op = [Dr | Ds | LIFT]) as
  * Op_hi*B_hi + Op_hi*B_lo + Op_lo*B_hi in 16-bit parts with FP32
  * accumulation on the matrix cores, and keep the geometric factors, normals
- * and surface Jacobians in FP64 on the device (split-FP16: 2D only; neither
- * with kernel = 1).  DGW_FP64 (section "Adding Generality", item "Double
- * Precision": the method run with double-precision fields) keeps the
- * fields, the RK residual, the operators, the factors and every operation
- * of the stage in FP64 (kernel 0 or 2: FP64 matrix cores; 1: the
+ * and surface Jacobians in FP64 on the device (split-FP16: 2D only; both
+ * run on their own kernels: kernel 1 or 3 is DGW_EINVAL).  DGW_FP64
+ * (section "Adding Generality", item "Double Precision": the method run
+ * with double-precision fields) keeps the fields, the RK residual, the
+ * operators, the factors and every operation of the stage in FP64 (kernel
+ * 0, 2 or 3: the derivative-first kernel on the FP64 matrix cores; 1: the
  * scalar-operand kernel); 2D only, and the FP32 device-pointer calls
  * (dgw_set_fields_dev, dgw_get_fields_dev) return DGW_EINVAL for it.
  * Measured accuracy is stated beside every result (relative L2 against
@@ -107,7 +108,8 @@ typedef struct {
     int32_t prec;        /* dgw_precision                                         */
     int32_t renumber;    /* 1 (default): space-filling-curve element order on GPU */
     int32_t device;      /* HIP device ordinal; -1 = host-only handle (setup only)*/
-    int32_t kernel;      /* stage kernel: 0 auto (MFMA), 1 scalar-operand VALU, 2 MFMA */
+    int32_t kernel;      /* 2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-
+                            operand MFMA, 3 derivative-first MFMA (FP32, FP64)     */
     void *hip_stream;    /* hipStream_t to launch on; NULL = library's own stream */
 } dgw_opts;
 

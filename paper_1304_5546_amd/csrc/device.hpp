@@ -56,7 +56,7 @@ struct StageArgs {
     const float *fgeo;
     const int *nbr;
     const float *ops;
-    const float *opsfrag;  // fused operator in MFMA A-fragment order (2D MFMA kernel)
+    const float *opsfrag;  // operators in MFMA A-fragment order, laid out for the launched kernel
     const int *itab;
     const double *geo64;   // FP64 copies of geo / fgeo (split-precision kernels)
     const double *fgeo64;
@@ -69,7 +69,7 @@ struct StageArgs {
     double *qout64;
     double *res64;
     const double *ops64;       // row-major Dr, Ds, LIFT (scalar-operand kernel)
-    const double *opsfrag64;   // A-fragment order (FP64 matrix-core kernel)
+    const double *opsfrag64;   // A-fragment order (derivative-first FP64 kernel)
     double a64, b64, dt64, alpha64;
     int Kp;
     int ntiles;
@@ -77,8 +77,9 @@ struct StageArgs {
     float a, b, dt, alpha;
 };
 
-// Kernel variants of the fused stage.
-enum StageVariant { kVariantAuto = 0, kVariantScalarOperand = 1, kVariantMfma = 2 };
+// Kernel variants of the fused stage (2D): fused-operand producer/consumer
+// MFMA kernel, scalar-operand VALU kernel, derivative-first MFMA kernel.
+enum StageVariant { kVariantAuto = 0, kVariantScalarOperand = 1, kVariantMfma = 2, kVariantDerivFirst = 3 };
 
 // Launch one fused stage: res <- a res + dt L(qin); qout <- qin + b res.
 hipError_t launch_stage(int dim, int N, bool material, int variant, const StageArgs &args, hipStream_t stream);
@@ -100,15 +101,17 @@ int blocks_per_cu_2d_mfma(int N, bool material);
 int blocks_per_cu_3d(int N);
 
 // FP64 2D stage on FP64 fields (a.qin64 / a.qout64 / a.res64, a.geo64 /
-// a.fgeo64, a.a64 / a.b64 / a.dt64 / a.alpha64): the scalar-operand kernel
-// (row-major a.ops64) or the matrix-core kernel (a.opsfrag64, persistent
-// grid of a.ngroups work-groups)
+// a.fgeo64, a.a64 / a.b64 / a.dt64 / a.alpha64, row-major a.ops64): the
+// scalar-operand kernel
 hipError_t launch_stage2d_fp64(int N, bool material, const StageArgs &a, hipStream_t s);
-hipError_t launch_stage2d_f64(int N, bool material, const StageArgs &a, hipStream_t s);
-int blocks_per_cu_2d_f64(int N, bool material);
-// fragment-ordered FP64 Dr, Ds, LIFT of the matrix-core kernel; with
-// out == nullptr returns the required length
-int opsfrag2d_f64(int N, const double *Dr, const double *Ds, const double *LIFT, double *out);
+// Derivative-first 2D MFMA stage, persistent grid of a.ngroups work-groups:
+// FP32 (a.qin / ..., operator fragments a.opsfrag) or FP64 (a.qin64 / ...,
+// a.opsfrag64)
+hipError_t launch_stage2d_df(int N, bool material, bool fp64, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_2d_df(int N, bool material, bool fp64);
+// its fragment-ordered Dr, Ds, LIFT; with out == nullptr returns the length
+int opsfrag2d_df(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
+int opsfrag2d_df64(int N, const double *Dr, const double *Ds, const double *LIFT, double *out);
 
 // Split-precision 2D stage (prec 1 = BF16 hi+lo, 2 = FP16 hi+lo), FP32
 // accumulation, FP64 geometric factors (geo64 / fgeo64).

@@ -223,8 +223,11 @@ int setup_device(dgw_solver *s) {
     if (s->fp64) {
         // FP64 fragments of the matrix-core kernel (the scalar-operand kernel
         // reads the row-major FP64 operators)
-        opsfrag64.resize(dgw::opsfrag2d_f64(s->N, nullptr, nullptr, nullptr, nullptr));
-        dgw::opsfrag2d_f64(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag64.data());
+        opsfrag64.resize(dgw::opsfrag2d_df64(s->N, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag2d_df64(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag64.data());
+    } else if (s->deriv_first) {
+        opsfrag.resize(dgw::opsfrag2d_df(s->N, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag2d_df(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
     } else if (split && dim == 3) {
         const int bytes = dgw::opsfrag3d_split(s->N, nullptr, nullptr, nullptr, nullptr, nullptr);
         opsfrag.resize(bytes / sizeof(float));
@@ -263,7 +266,7 @@ int setup_device(dgw_solver *s) {
     {
         int ncu = 0;
         DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-        const int per_cu = s->fp64 ? dgw::blocks_per_cu_2d_f64(s->N, s->material)
+        const int per_cu = s->fp64 || s->deriv_first ? dgw::blocks_per_cu_2d_df(s->N, s->material, s->fp64)
                            : split ? (dim == 2 ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
                                                : dgw::blocks_per_cu_3d_split(s->N))
                                    : (dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
@@ -337,7 +340,8 @@ void set_stage(const dgw_solver *s, dgw::StageArgs &a, double ca, double cb, dou
 hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t st) {
     if (s->fp64)
         return s->opts.kernel == dgw::kVariantScalarOperand ? dgw::launch_stage2d_fp64(s->N, s->material, a, st)
-                                                            : dgw::launch_stage2d_f64(s->N, s->material, a, st);
+                                                            : dgw::launch_stage2d_df(s->N, s->material, true, a, st);
+    if (s->deriv_first) return dgw::launch_stage2d_df(s->N, s->material, false, a, st);
     if (s->opts.prec != DGW_FP32)
         return s->dim == 2 ? dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st)
                            : dgw::launch_stage3d_split(s->N, a, st);
@@ -493,14 +497,16 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
         return fail(DGW_EINVAL, "unknown precision variant");
     if ((opts.prec == DGW_SPLIT_FP16 || opts.prec == DGW_FP64) && mesh->dim != 2)
         return fail(DGW_EINVAL, "the 3D path has the FP32 and split-BF16 variants");
-    if (opts.kernel < 0 || opts.kernel > 2) return fail(DGW_EINVAL, "kernel variant must be 0, 1 or 2");
-    if ((opts.prec == DGW_SPLIT_BF16 || opts.prec == DGW_SPLIT_FP16) && opts.kernel == 1)
-        return fail(DGW_EINVAL, "split-precision variants run on the matrix cores only (kernel 0 or 2)");
+    if (opts.kernel < 0 || opts.kernel > 3) return fail(DGW_EINVAL, "kernel variant must be 0, 1, 2 or 3");
+    if ((opts.prec == DGW_SPLIT_BF16 || opts.prec == DGW_SPLIT_FP16) && (opts.kernel == 1 || opts.kernel == 3))
+        return fail(DGW_EINVAL, "split-precision variants run on their own matrix-core kernels (kernel 0 or 2)");
+    if (opts.kernel == 3 && mesh->dim != 2) return fail(DGW_EINVAL, "kernel 3 is a 2D kernel");
     auto t0 = std::chrono::steady_clock::now();
     dgw_solver *s = new (std::nothrow) dgw_solver();
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
     s->opts = opts;
     s->fp64 = opts.prec == DGW_FP64;
+    s->deriv_first = opts.prec == DGW_FP32 && mesh->dim == 2 && opts.kernel == dgw::kVariantDerivFirst;
     s->dim = mesh->dim;
     s->N = order;
     try {

@@ -181,6 +181,7 @@ void setup(dgw_server *S, Req *r) {
         dgw_opts_default(&o);
         o.alpha = r->alpha;
         o.prec = r->prec;
+        o.kernel = dgw::kVariantMfma;  // the batched launches run the fused-operand kernel
         o.device = S->opts.device;
         rc = dgw_create(&m, r->order, &o, &s);
         if (rc == DGW_OK) rc = r->q0.empty() ? dgw_set_cavity_mode(s, r->mode) : dgw_set_fields(s, r->q0.data());

@@ -28,6 +28,7 @@ struct dgw_solver {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool fp64 = false;  // DGW_FP64: fields in q64 / res64, FP32 q / res unused
+    bool deriv_first = false;  // FP32 2D on the derivative-first kernel
     float *q[2] = {nullptr, nullptr};
     float *res = nullptr;
     double *q64[2] = {nullptr, nullptr};
