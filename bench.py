@@ -170,6 +170,8 @@ def main():
                     help="2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-operand MFMA, 3 derivative-first MFMA")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "split_bf16", "split_fp16", "fp64"],
                     help="arithmetic of the timed path (value and roofline)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every kernel variant and launch shape first (dgw_autotune) and time the fastest")
     ap.add_argument("--serve", action="store_true", help="run the serving configuration instead")
     ap.add_argument("--serve-n", type=int, default=256, help="requests in the serving run")
     ap.add_argument("--no-variants", action="store_true",
@@ -221,6 +223,7 @@ def main():
         solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec)
         dt = solver.cfl_dt()
         solver.set_cavity_mode(*mode)
+        solver.tune = solver.autotune() if args.autotune else None
         solver.launch_steps(args.warmup, dt, stream)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -247,15 +250,16 @@ def main():
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
     pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2, "fp64": 3}[args.prec]
+    variant = solver.tune["kernel"] if solver.tune else args.kernel
     if dim == 3:
         kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
     elif pcode == 3:
-        kname = f"stage2d_kernel<double, {N}, false>" if args.kernel == 1 else f"stage2d_df_kernel<double, {N}, false>"
+        kname = f"stage2d_kernel<double, {N}, false>" if variant == 1 else f"stage2d_df_kernel<double, {N}, false>"
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
         kname = {1: f"stage2d_kernel<float, {N}, false>",
-                 3: f"stage2d_df_kernel<float, {N}, false>"}.get(args.kernel, f"stage2d_mfma_kernel<{N}, false, false>")
+                 3: f"stage2d_df_kernel<float, {N}, false>"}.get(variant, f"stage2d_mfma_kernel<{N}, false, false>")
     out = {
         "metric": METRIC,
         "value": value,
@@ -278,6 +282,8 @@ def main():
                      "kernel": kname, "avg_launch_us": launch_s * 1e6,
                      "bytes_per_launch": bytes_per_launch},
     }
+    if solver.tune:
+        out["autotune"] = solver.tune
     solver.close()
     if not args.no_variants:
         # the same timed run for every precision variant, each with its

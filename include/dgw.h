@@ -196,6 +196,32 @@ int dgw_get_fields_dev(dgw_solver *s, float *q_dev, void *stream);
 /* Launch `nsteps` steps on `stream` without waiting (for timing by the
  * caller); dt must be > 0. */
 int dgw_launch_steps(dgw_solver *s, int64_t nsteps, double dt, void *stream);
+/* Automated tuning over kernel variants (sections "Rethinking the Work
+ * Partition" and "Using Run-Time Code Generation": time each variant of the
+ * work partition and keep the fastest): time `stages` fused stages (<= 0: 10, after 2 untimed ones)
+ * of every candidate on this solver's own mesh and buffers, and keep the
+ * fastest for all later launches.  Candidates: each 2D kernel that serves the
+ * solver's arithmetic (FP32: fused-operand MFMA, derivative-first MFMA,
+ * scalar-operand VALU; FP64: derivative-first MFMA, VALU; split and 3D: their
+ * one kernel), each persistent kernel at 1 .. min(occupancy, 4) work-groups
+ * per CU.  All candidates compute the same arithmetic per element, so results
+ * do not depend on the choice beyond the rounding differences between
+ * kernels.  The fields, the residual and the time are restored bitwise
+ * afterwards.  Allocates two state-sized device buffers for the duration of
+ * the call; the solver must not be in use on another thread.  out may be
+ * NULL.  Errors: ENODEVICE, ENOMEM, EDEVICE. */
+#define DGW_TUNE_MAX 16
+typedef struct {
+    int32_t kernel;          /* chosen variant (dgw_opts.kernel numbering)           */
+    int32_t groups_per_cu;   /* chosen persistent work-groups per CU (0: not persistent) */
+    double best_us;          /* its mean stage time                                  */
+    int32_t n_tried;
+    int32_t tried_kernel[DGW_TUNE_MAX];
+    int32_t tried_groups_per_cu[DGW_TUNE_MAX];
+    double tried_us[DGW_TUNE_MAX];
+} dgw_tune_info;
+int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out);
+
 /* Kernel name and per-launch algorithmic HBM bytes and flops of one fused
  * stage (the units behind the roofline figures). */
 int dgw_stage_cost(const dgw_solver *s, double *bytes, double *flops);

@@ -57,10 +57,10 @@ int64_t solver_footprint(int dim, int order, int64_t K, bool material, int prec)
     int64_t b = 3 * nf * Np * Kp * wq;                   // q ping-pong and res
     b += (G + Nf * FG) * Kp * 4 + Nf * Kp * 4;          // factors and face records
     if (prec != DGW_FP32) b += (G + Nf * FG) * Kp * 8;  // FP64 factors
-    if (prec == DGW_FP64) {  // FP64 operators, row-major and in fragment order
-        const int64_t MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nf * Nfp + 3) / 4;
+    const int64_t MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nf * Nfp + 3) / 4;
+    if (prec == DGW_FP64)  // FP64 operators, row-major and in fragment order
         b += Np * (dim * Np + Nf * Nfp) * 8 + (2 * MT * KV + MT * KL) * 64 * 8;
-    }
+    if (prec == DGW_FP32 && dim == 2) b += (2 * MT * KV + MT * KL) * 64 * 4;  // derivative-first fragments
     b += Kp * 4 + Kp * 8 + dim * Np * Kp * 8;           // permutation, J, node coordinates
     if (material) b += nf * Kp * 8;                     // energy weights
     b += 4 * Np * (dim * Np + Nf * Nfp) * 4 + Np * Np * 8 + 64 * 1024;  // operators, tables, scratch
@@ -100,12 +100,34 @@ int upload(T *dst, const std::vector<T> &src) {
     return DGW_OK;
 }
 
+// Resident work-groups per CU of the persistent kernel of `variant` on this
+// solver (0: the variant is not persistent).
+int occupancy_of(const dgw_solver *s, int variant) {
+    const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
+    if (s->dim == 3) return split ? dgw::blocks_per_cu_3d_split(s->N) : dgw::blocks_per_cu_3d(s->N);
+    if (split) return dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec);
+    if (variant == dgw::kVariantScalarOperand) return 0;
+    if (s->fp64 || variant == dgw::kVariantDerivFirst) return dgw::blocks_per_cu_2d_df(s->N, s->material, s->fp64);
+    return dgw::blocks_per_cu_2d_mfma(s->N, s->material);
+}
+
+// Persistent grid of `gpc` work-groups per CU: a multiple of the 8 XCDs, no
+// more groups than tiles (rounded up to the 8 XCDs).
+void set_grid(dgw_solver *s, int gpc) {
+    s->gpc = gpc;
+    const int ntiles = (int)(s->Kp / dgw::kTile);
+    int ng = std::max(1, s->ncu) * std::max(1, gpc);
+    ng = std::min(ng, (ntiles + 7) / 8 * 8);
+    s->ngroups = std::max(8, ng / 8 * 8);
+}
+
 void free_device(dgw_solver *s) {
     if (!s->on_device) return;
     hipSetDevice(s->opts.device);
     void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->opsfrag_d, s->nbr_d, s->itab_d, s->perm_d,
                     s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d,
-                    s->geo64_d, s->fgeo64_d, s->q64[0], s->q64[1], s->res64, s->ops64_d, s->opsfrag64_d};
+                    s->geo64_d, s->fgeo64_d, s->q64[0], s->q64[1], s->res64, s->ops64_d, s->opsfrag64_d,
+                    s->opsfrag_df_d};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (s->ev0) hipEventDestroy(s->ev0);
@@ -218,16 +240,13 @@ int setup_device(dgw_solver *s) {
     std::vector<int> permv(s->perm.begin(), s->perm.end());
     const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
     const bool need64 = s->opts.prec != DGW_FP32;  // FP64 factors on the device
-    std::vector<float> opsfrag;
+    std::vector<float> opsfrag, opsfrag_df;
     std::vector<double> opsfrag64;
     if (s->fp64) {
         // FP64 fragments of the matrix-core kernel (the scalar-operand kernel
         // reads the row-major FP64 operators)
         opsfrag64.resize(dgw::opsfrag2d_df64(s->N, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag2d_df64(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag64.data());
-    } else if (s->deriv_first) {
-        opsfrag.resize(dgw::opsfrag2d_df(s->N, nullptr, nullptr, nullptr, nullptr));
-        dgw::opsfrag2d_df(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
     } else if (split && dim == 3) {
         const int bytes = dgw::opsfrag3d_split(s->N, nullptr, nullptr, nullptr, nullptr, nullptr);
         opsfrag.resize(bytes / sizeof(float));
@@ -248,6 +267,9 @@ int setup_device(dgw_solver *s) {
                     return fail(DGW_EINVAL, "internal: face node order mismatch");
         opsfrag.resize(dgw::opsfrag2d(s->N, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag2d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
+        // and those of the derivative-first kernel, so that either can run
+        opsfrag_df.resize(dgw::opsfrag2d_df(s->N, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag2d_df(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag_df.data());
     } else {
         opsfrag.resize(dgw::opsfrag3d(s->N, nullptr, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag3d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.Dt.a.data(), R.LIFT.a.data(), opsfrag.data());
@@ -261,21 +283,12 @@ int setup_device(dgw_solver *s) {
         (rc = dalloc(&s->partial_d, 2 * kRedBlocks)) || (rc = dalloc(&s->opsfrag_d, opsfrag.size())))
         return rc;
     if (!opsfrag.empty() && (rc = upload(s->opsfrag_d, opsfrag))) return rc;
-    // persistent grid: every CU filled to its occupancy, a multiple of the 8
-    // XCDs, no more groups than tiles (rounded up to the 8 XCDs)
-    {
-        int ncu = 0;
-        DGW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-        const int per_cu = s->fp64 || s->deriv_first ? dgw::blocks_per_cu_2d_df(s->N, s->material, s->fp64)
-                           : split ? (dim == 2 ? dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec)
-                                               : dgw::blocks_per_cu_3d_split(s->N))
-                                   : (dim == 2 ? dgw::blocks_per_cu_2d_mfma(s->N, s->material)
-                                               : dgw::blocks_per_cu_3d(s->N));
-        const int ntiles = (int)(Kp / dgw::kTile);
-        int ng = std::max(1, ncu) * per_cu;
-        ng = std::min(ng, (ntiles + 7) / 8 * 8);
-        s->ngroups = std::max(8, ng / 8 * 8);
-    }
+    if (!opsfrag_df.empty() &&
+        ((rc = dalloc(&s->opsfrag_df_d, opsfrag_df.size())) || (rc = upload(s->opsfrag_df_d, opsfrag_df))))
+        return rc;
+    // persistent grid: every CU filled to its occupancy
+    DGW_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
+    set_grid(s, occupancy_of(s, s->variant));
     if (dim == 3 && (rc = dalloc(&s->z_d, Z.size()))) return rc;
     if (s->material && (rc = dalloc(&s->w_d, w.size()))) return rc;
     std::vector<float> geo32(geo.begin(), geo.end()), fgeo32(fgeo.begin(), fgeo.end());
@@ -310,7 +323,7 @@ dgw::StageArgs stage_args(const dgw_solver *s) {
     a.fgeo64 = s->fgeo64_d;
     a.nbr = s->nbr_d;
     a.ops = s->ops_d;
-    a.opsfrag = s->opsfrag_d;
+    a.opsfrag = s->dim == 2 && !s->fp64 && s->variant == dgw::kVariantDerivFirst ? s->opsfrag_df_d : s->opsfrag_d;
     a.itab = s->itab_d;
     a.Kp = (int)s->Kp;
     a.ntiles = (int)(s->Kp / dgw::kTile);
@@ -339,13 +352,14 @@ void set_stage(const dgw_solver *s, dgw::StageArgs &a, double ca, double cb, dou
 
 hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t st) {
     if (s->fp64)
-        return s->opts.kernel == dgw::kVariantScalarOperand ? dgw::launch_stage2d_fp64(s->N, s->material, a, st)
-                                                            : dgw::launch_stage2d_df(s->N, s->material, true, a, st);
-    if (s->deriv_first) return dgw::launch_stage2d_df(s->N, s->material, false, a, st);
+        return s->variant == dgw::kVariantScalarOperand ? dgw::launch_stage2d_fp64(s->N, s->material, a, st)
+                                                        : dgw::launch_stage2d_df(s->N, s->material, true, a, st);
     if (s->opts.prec != DGW_FP32)
         return s->dim == 2 ? dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st)
                            : dgw::launch_stage3d_split(s->N, a, st);
-    return dgw::launch_stage(s->dim, s->N, s->material, s->opts.kernel, a, st);
+    if (s->dim == 2 && s->variant == dgw::kVariantDerivFirst)
+        return dgw::launch_stage2d_df(s->N, s->material, false, a, st);
+    return dgw::launch_stage(s->dim, s->N, s->material, s->variant, a, st);
 }
 
 int launch_steps_impl(dgw_solver *s, int64_t nsteps, double dt, hipStream_t st) {
@@ -506,7 +520,11 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
     s->opts = opts;
     s->fp64 = opts.prec == DGW_FP64;
-    s->deriv_first = opts.prec == DGW_FP32 && mesh->dim == 2 && opts.kernel == dgw::kVariantDerivFirst;
+    // the kernel that runs: 2D FP32 auto = the fused-operand MFMA kernel,
+    // FP64 auto = the derivative-first one; split and 3D have one kernel each
+    s->variant = opts.kernel == dgw::kVariantAuto
+                     ? (s->fp64 ? dgw::kVariantDerivFirst : dgw::kVariantMfma)
+                     : (s->fp64 && opts.kernel == dgw::kVariantMfma ? dgw::kVariantDerivFirst : opts.kernel);
     s->dim = mesh->dim;
     s->N = order;
     try {
@@ -793,6 +811,97 @@ int dgw_launch_steps(dgw_solver *s, int64_t nsteps, double dt, void *stream) {
     hipStream_t st = stream ? (hipStream_t)stream : s->stream;
     if ((rc = launch_steps_impl(s, nsteps, dt, st))) return rc;
     s->t += nsteps * dt;
+    return DGW_OK;
+}
+
+int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (stages <= 0) stages = 10;
+    DGW_HIP(hipSetDevice(s->opts.device));
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    // the candidates: every stage kernel of this dimension and arithmetic, each
+    // persistent one at every work-group count per CU up to its occupancy
+    std::vector<std::pair<int, int>> cand;  // (variant, groups per CU)
+    std::vector<int> variants;
+    const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
+    if (s->dim == 2 && !split)
+        variants = s->fp64 ? std::vector<int>{dgw::kVariantDerivFirst, dgw::kVariantScalarOperand}
+                           : std::vector<int>{dgw::kVariantMfma, dgw::kVariantDerivFirst, dgw::kVariantScalarOperand};
+    else
+        variants = {s->variant};
+    for (int v : variants) {
+        const int occ = occupancy_of(s, v);
+        if (occ == 0)
+            cand.push_back({v, 0});
+        else
+            for (int g = 1; g <= std::min(occ, 4); ++g) cand.push_back({v, g});
+    }
+    if ((int)cand.size() > DGW_TUNE_MAX) cand.resize(DGW_TUNE_MAX);
+    // save the state (fields, residual, ping-pong index), try every
+    // candidate on the solver's own buffers, restore the state bitwise
+    const size_t nstate = (size_t)s->nf * s->Np * s->Kp, bytes = nstate * (s->fp64 ? 8 : 4);
+    void *cur_d = s->fp64 ? (void *)s->q64[s->cur] : (void *)s->q[s->cur];
+    void *res_d = s->fp64 ? (void *)s->res64 : (void *)s->res;
+    void *save = nullptr;
+    if (hipMalloc(&save, 2 * bytes) != hipSuccess) return fail(DGW_ENOMEM, "autotune: no device memory for the saved state");
+    struct Free {
+        void *p;
+        ~Free() { hipFree(p); }
+    } free_save{save};
+    const int cur0 = s->cur, var0 = s->variant, gpc0 = s->gpc;
+    DGW_HIP(hipMemcpyAsync(save, cur_d, bytes, hipMemcpyDeviceToDevice, s->stream));
+    DGW_HIP(hipMemcpyAsync((char *)save + bytes, res_d, bytes, hipMemcpyDeviceToDevice, s->stream));
+    dgw_tune_info info{};
+    int best = -1;
+    double best_us = 0;
+    const double dt = s->dt_cfl;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        s->variant = cand[i].first;
+        set_grid(s, cand[i].second);
+        dgw::StageArgs a = stage_args(s);
+        auto run = [&](int n) -> int {
+            for (int k = 0; k < n; ++k) {
+                set_stage(s, a, kRkA[k % 5], kRkB[k % 5], dt);
+                DGW_HIP(launch_one(s, a, s->stream));
+                s->cur = 1 - s->cur;
+            }
+            return DGW_OK;
+        };
+        if ((rc = run(2))) break;
+        DGW_HIP(hipEventRecord(s->ev0, s->stream));
+        if ((rc = run(stages))) break;
+        DGW_HIP(hipEventRecord(s->ev1, s->stream));
+        DGW_HIP(hipEventSynchronize(s->ev1));
+        float ms = 0;
+        DGW_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+        const double us = 1e3 * ms / stages;
+        info.tried_kernel[i] = cand[i].first;
+        info.tried_groups_per_cu[i] = cand[i].second;
+        info.tried_us[i] = us;
+        info.n_tried = (int)i + 1;
+        if (best < 0 || us < best_us) {
+            best = (int)i;
+            best_us = us;
+        }
+    }
+    // restore the state, keep the fastest candidate (or the old choice on error)
+    s->cur = cur0;
+    cur_d = s->fp64 ? (void *)s->q64[s->cur] : (void *)s->q[s->cur];
+    DGW_HIP(hipMemcpyAsync(cur_d, save, bytes, hipMemcpyDeviceToDevice, s->stream));
+    DGW_HIP(hipMemcpyAsync(res_d, (char *)save + bytes, bytes, hipMemcpyDeviceToDevice, s->stream));
+    DGW_HIP(hipStreamSynchronize(s->stream));
+    if (rc || best < 0) {
+        s->variant = var0;
+        set_grid(s, gpc0);
+        return rc ? rc : fail(DGW_EINVAL, "autotune: no candidate");
+    }
+    s->variant = cand[best].first;
+    set_grid(s, cand[best].second);
+    info.kernel = s->variant;
+    info.groups_per_cu = s->gpc;
+    info.best_us = best_us;
+    if (out) *out = info;
     return DGW_OK;
 }
 

@@ -28,11 +28,13 @@ struct dgw_solver {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool fp64 = false;  // DGW_FP64: fields in q64 / res64, FP32 q / res unused
-    bool deriv_first = false;  // FP32 2D on the derivative-first kernel
+    int variant = 2;   // 2D stage kernel that runs (dgw::StageVariant, resolved)
+    int ncu = 0, gpc = 0;  // CUs of the device, persistent work-groups per CU
     float *q[2] = {nullptr, nullptr};
     float *res = nullptr;
     double *q64[2] = {nullptr, nullptr};
     double *res64 = nullptr, *ops64_d = nullptr, *opsfrag64_d = nullptr;
+    float *opsfrag_df_d = nullptr;  // FP32 2D: fragments of the derivative-first kernel
     int cur = 0;
     float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr, *opsfrag_d = nullptr;
     double *geo64_d = nullptr, *fgeo64_d = nullptr;  // split-precision and FP64 variants only

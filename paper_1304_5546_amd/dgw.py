@@ -49,6 +49,15 @@ class Info(C.Structure):
                 ("solve_ms", C.c_double), ("dof_updates_per_s", C.c_double)]
 
 
+TUNE_MAX = 16
+
+
+class TuneInfo(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("groups_per_cu", C.c_int32), ("best_us", C.c_double),
+                ("n_tried", C.c_int32), ("tried_kernel", C.c_int32 * TUNE_MAX),
+                ("tried_groups_per_cu", C.c_int32 * TUNE_MAX), ("tried_us", C.c_double * TUNE_MAX)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("device", C.c_int32),
                 ("setup_threads", C.c_int32), ("max_chunk_steps", C.c_int32)]
@@ -114,6 +123,7 @@ def lib() -> C.CDLL:
             "dgw_get_fields_dev": (C.c_int, [P, P, P]),
             "dgw_launch_steps": (C.c_int, [P, I64, D, P]),
             "dgw_stage_cost": (C.c_int, [P, P, P]),
+            "dgw_autotune": (C.c_int, [P, I32, P]),
             "dgw_footprint": (C.c_int, [P, I32, P, P]),
             "dgw_server_create": (C.c_int, [P, P]),
             "dgw_submit": (C.c_int, [P, P, P]),
@@ -275,6 +285,17 @@ class Solver:
         i = Info()
         _check(lib().dgw_last_info(self._h, C.byref(i)), "dgw_last_info")
         return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    def autotune(self, stages: int = 10) -> dict:
+        """Time every kernel variant and launch shape that serves this solve
+        (dgw_autotune) and keep the fastest; returns the choice and the
+        timings of all candidates."""
+        t = TuneInfo()
+        _check(lib().dgw_autotune(self._h, int(stages), C.byref(t)), "dgw_autotune")
+        n = t.n_tried
+        return {"kernel": t.kernel, "groups_per_cu": t.groups_per_cu, "best_us": t.best_us,
+                "tried": [{"kernel": t.tried_kernel[i], "groups_per_cu": t.tried_groups_per_cu[i],
+                           "us": t.tried_us[i]} for i in range(n)]}
 
     def stage_cost(self) -> tuple[float, float]:
         b, f = C.c_double(), C.c_double()

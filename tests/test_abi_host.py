@@ -145,6 +145,9 @@ def test_error_paths_before_any_device_call():
     # the FP64 field path is 2D only
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="fp64", device=-1))
     dgw.Solver(m, 3, prec="fp64", kernel=1, device=-1).close()
+    # tuning needs a device
+    with dgw.Solver(m, 3, device=-1) as h:
+        _expect("DGW_ENODEVICE", lambda: h.autotune())
     # NULL arguments at the raw ABI
     L = dgw.lib()
     h = C.c_void_p()
