@@ -250,7 +250,7 @@ def main():
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
     pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2, "fp64": 3}[args.prec]
-    variant = solver.tune["kernel"] if solver.tune else args.kernel
+    variant = solver.info()["kernel"]
     if dim == 3:
         kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
     elif pcode == 3:

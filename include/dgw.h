@@ -108,8 +108,9 @@ typedef struct {
     int32_t prec;        /* dgw_precision                                         */
     int32_t renumber;    /* 1 (default): space-filling-curve element order on GPU */
     int32_t device;      /* HIP device ordinal; -1 = host-only handle (setup only)*/
-    int32_t kernel;      /* 2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-
-                            operand MFMA, 3 derivative-first MFMA (FP32, FP64)     */
+    int32_t kernel;      /* 2D stage kernel: 0 auto (FP32: 3 up to order 6, else 2;
+                            FP64: 3), 1 scalar-operand VALU, 2 fused-operand
+                            MFMA, 3 derivative-first MFMA (FP32, FP64)            */
     void *hip_stream;    /* hipStream_t to launch on; NULL = library's own stream */
 } dgw_opts;
 
@@ -139,6 +140,8 @@ typedef struct {
     double setup_s;           /* host setup + upload of dgw_create            */
     double solve_ms;          /* device time of the last advance (HIP events) */
     double dof_updates_per_s; /* n_fields*K*Np*steps / solve time             */
+    int32_t kernel;           /* stage kernel in use (dgw_opts.kernel numbering, resolved) */
+    int32_t groups_per_cu;    /* persistent work-groups per CU (0: not persistent)     */
 } dgw_info;
 
 /* Set up the discretisation of order `order` on `mesh` (host FP64), upload

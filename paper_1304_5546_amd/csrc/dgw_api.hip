@@ -520,10 +520,13 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
     s->opts = opts;
     s->fp64 = opts.prec == DGW_FP64;
-    // the kernel that runs: 2D FP32 auto = the fused-operand MFMA kernel,
-    // FP64 auto = the derivative-first one; split and 3D have one kernel each
+    // the kernel that runs: 2D FP32 auto = derivative-first up to order 6,
+    // fused-operand MFMA above; FP64 auto = derivative-first; split and 3D
+    // have one kernel each
+    const bool plain32 = opts.prec == DGW_FP32 && s->dim == 2;
     s->variant = opts.kernel == dgw::kVariantAuto
-                     ? (s->fp64 ? dgw::kVariantDerivFirst : dgw::kVariantMfma)
+                     ? (s->fp64 || (plain32 && dgw::auto_deriv_first(order)) ? dgw::kVariantDerivFirst
+                                                                             : dgw::kVariantMfma)
                      : (s->fp64 && opts.kernel == dgw::kVariantMfma ? dgw::kVariantDerivFirst : opts.kernel);
     s->dim = mesh->dim;
     s->N = order;
@@ -776,6 +779,8 @@ int dgw_cavity_error(dgw_solver *s, const int32_t mode[3], double t, double *rel
 int dgw_last_info(const dgw_solver *s, dgw_info *info) {
     if (!s || !info) return fail(DGW_EINVAL, "NULL argument");
     *info = s->info;
+    info->kernel = s->variant;
+    info->groups_per_cu = s->gpc;
     return DGW_OK;
 }
 

@@ -94,7 +94,9 @@ struct Arith<float> {
     __device__ static float alpha(const StageArgs &A) { return A.alpha; }
 };
 
-template <typename R, int N, bool MAT>
+// P elements per lane (P = 2: lane c of an MFMA N-tile pair works on
+// elements 2 c and 2 c + 1, read and written as one 8-byte access).
+template <typename R, int N, bool MAT, int P>
 struct TriD {
     static constexpr int Np = (N + 1) * (N + 2) / 2;
     static constexpr int Nfp = N + 1;
@@ -107,14 +109,14 @@ struct TriD {
     static constexpr int NT = Nafp + 3 * 2 * Nfp;  // own face nodes, partner-node table
     static constexpr int G = MAT ? 6 : 4;        // per-element factor rows
     static constexpr int FG = MAT ? 6 : 3;       // per-face data rows
-    static constexpr int FS = 17;                // LDS row stride of the field copies
+    static constexpr int FS = 16 * P + 1;        // LDS row stride of the field copies
     static constexpr int FW = 3 * Np * FS;       // values of one wave's field copy
     // waves per work-group: as many as the LDS holds (field copies plus one
     // shared copy of the operators), at most WMAX: 12 (3 per SIMD, which
-    // leaves each wave the ~170 registers that FP64 from order 5 and FP32
-    // from order 7 need), else 16
+    // leaves each wave the ~170 registers that FP64 from order 5, FP32 from
+    // order 7 and FP32 element pairs need), else 16
     static constexpr int LDS_MAX = 160 * 1024;
-    static constexpr int WMAX = (sizeof(R) == 8 || N >= 7) ? 12 : 16;
+    static constexpr int WMAX = (sizeof(R) == 8 || N >= 7 || P == 2) ? 12 : 16;
     static constexpr int FIXED = (AV + AL) * (int)sizeof(R) + NT * 4;
     static constexpr int WPB0 = (LDS_MAX - FIXED) / (FW * (int)sizeof(R));
     static constexpr int WPB = WPB0 >= WMAX ? WMAX : (WPB0 >= 12 ? 12 : (WPB0 >= 8 ? 8 : 4));
@@ -125,21 +127,89 @@ struct TriD {
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ int bload_i(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(int, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+
+// P consecutive values of a row (one access), returned by value
+template <typename R, int P>
+struct PV {
+    R v[P];
+};
+template <typename R, int P>
+__device__ __forceinline__ PV<R, P> loadp(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    PV<R, P> out;
+    if constexpr (P == 1) {
+        out.v[0] = Arith<R>::load(r, voff, soff);
+    } else {
+        static_assert(sizeof(R) == 4 && P == 2, "element pairs are FP32 only");
+        // through a 64-bit integer: extracting the elements of the two-dword
+        // result directly gets the load narrowed to its first dword by this
+        // compiler (both elements then read the same value)
+        const unsigned long long u =
+            __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        out.v[0] = __builtin_bit_cast(R, (unsigned)u);
+        out.v[1] = __builtin_bit_cast(R, (unsigned)(u >> 32));
+    }
+    return out;
+}
+template <int P>
+__device__ __forceinline__ PV<int, P> loadp_i(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    PV<int, P> out;
+    if constexpr (P == 1) {
+        out.v[0] = __builtin_bit_cast(int, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else {
+        const unsigned long long u =
+            __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        out.v[0] = (int)(unsigned)u;
+        out.v[1] = (int)(unsigned)(u >> 32);
+    }
+    return out;
+}
+template <typename R, int P>
+__device__ __forceinline__ void storep(__amdgpu_buffer_rsrc_t r, PV<R, P> x, unsigned voff, unsigned soff) {
+    if constexpr (P == 1) {
+        Arith<R>::store(r, x.v[0], voff, soff);
+    } else {
+        const u32x2 u = {__builtin_bit_cast(unsigned, x.v[0]), __builtin_bit_cast(unsigned, x.v[1])};
+        __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, 0);
+    }
+}
+
+// Buffers of the solve that owns global tile t, and t's index inside it
+// (batched launches: a wave-uniform lookup of the solve's descriptor).
+template <typename R>
+struct DfSrc {
+    const R *qin;
+    R *qout, *res;
+    const R *geo, *fgeo;
+    const int *nbr;
+    int tile;
+    R dt;
+};
+template <typename R, bool BATCH>
+__device__ __forceinline__ DfSrc<R> df_src(const StageArgs &A, int t) {
+    using X = Arith<R>;
+    if constexpr (!BATCH) {
+        return DfSrc<R>{X::qin(A), X::qout(A), X::res(A), X::geo(A), X::fgeo(A), A.nbr, t, X::dt(A)};
+    } else {
+        static_assert(sizeof(R) == 4, "batched launches are FP32");
+        const int r = __builtin_amdgcn_readfirstlane(A.tile_req[t]);
+        const BatchDesc &d = A.batch[r];
+        const int ci = (d.cur0 ^ A.parity) & 1;
+        return DfSrc<R>{d.q[ci], d.q[ci ^ 1], d.res, d.geo, d.fgeo, d.nbr, t - d.tile0, d.dt};
+    }
 }
 
 }  // namespace
 
-template <typename R, int N, bool MAT>
-__global__ void __launch_bounds__((64 * TriD<R, N, MAT>::WPB)) stage2d_df_kernel(StageArgs A) {
-    using T = TriD<R, N, MAT>;
+template <typename R, int N, bool MAT, int P, bool BATCH>
+__global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_kernel(StageArgs A) {
+    using T = TriD<R, N, MAT, P>;
     using X = Arith<R>;
     using V4 = typename X::V4;
     constexpr unsigned W = sizeof(R);  // bytes per value
     constexpr unsigned ROW = 64 * W;   // bytes per tile row
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, MT = T::MT, KV = T::KV, KL = T::KL;
     constexpr int AV = T::AV, AL = T::AL, NT = T::NT, G = T::G, FG = T::FG, FS = T::FS, WPB = T::WPB;
+    constexpr int UPT = 4 / P;  // work units per 64-element tile
     __shared__ R sA[AV + AL];
     __shared__ int stab[NT];
     __shared__ R sF[WPB][T::FW];
@@ -152,9 +222,9 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT>::WPB)) stage2d_df_kernel
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     R *F = sF[w];
 
-    // work units (16-element quarters of tiles) of this XCD: a contiguous
-    // range, dealt round-robin to its waves
-    const int nunits = 4 * A.ntiles;
+    // work units (16 P elements of a tile) of this XCD: a contiguous range,
+    // dealt round-robin to its waves
+    const int nunits = UPT * A.ntiles;
     const int x = blockIdx.x & 7, bi = blockIdx.x >> 3, GB = gridDim.x >> 3;
     const int q8 = nunits >> 3, r8 = nunits & 7;
     const int xbase = x * q8 + (x < r8 ? x : r8), xcount = q8 + (x < r8 ? 1 : 0);
@@ -163,171 +233,226 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT>::WPB)) stage2d_df_kernel
 
     for (int ul = bi * WPB + w; ul < xcount; ul += GB * WPB) {
         const int unit = xbase + ul;
-        const int tile = unit >> 2;
+        const DfSrc<R> S = df_src<R, BATCH>(A, unit / UPT);
+        const int tile = S.tile;  // tile within the solve
         // lane indices opaque to the compiler, recomputed per work unit
         int lane = lane0;
         asm volatile("" : "+v"(lane));
         const int g = lane >> 4, c = lane & 15;
-        const int col = 16 * (unit & 3) + c;
+        const int col = 16 * P * (unit % UPT) + P * c;       // the lane's first element in the tile
         const unsigned vcol = (unsigned)col * W;             // column within a row
         const unsigned vrow = (unsigned)(g * 64 + col) * W;  // row 4 ks + g of a K-step
-        const __amdgpu_buffer_rsrc_t rq = rsrc(X::qin(A) + (size_t)tile * (3 * Np * 64), TB);
+        const __amdgpu_buffer_rsrc_t rq = rsrc(S.qin + (size_t)tile * (3 * Np * 64), TB);
 
-        R gf[G];
+        R gf[G][P];
         {
-            const __amdgpu_buffer_rsrc_t rg = rsrc(X::geo(A) + (size_t)tile * (G * 64), G * ROW);
+            const __amdgpu_buffer_rsrc_t rg = rsrc(S.geo + (size_t)tile * (G * 64), G * ROW);
 #pragma unroll
-            for (int q = 0; q < G; ++q) gf[q] = X::load(rg, vcol, q * ROW);
+            for (int q = 0; q < G; ++q) {
+                const PV<R, P> t = loadp<R, P>(rg, vcol, q * ROW);
+#pragma unroll
+                for (int p = 0; p < P; ++p) gf[q][p] = t.v[p];
+            }
         }
-        // face records and face data of the element, held as scalars
-        const __amdgpu_buffer_rsrc_t rn = rsrc(A.nbr + (size_t)tile * (3 * 64), 3 * 64 * 4);
-        const __amdgpu_buffer_rsrc_t rf = rsrc(X::fgeo(A) + (size_t)tile * (3 * FG * 64), 3 * FG * ROW);
+        // face records and face data of the elements, held as scalars
+        const __amdgpu_buffer_rsrc_t rn = rsrc(S.nbr + (size_t)tile * (3 * 64), 3 * 64 * 4);
+        const __amdgpu_buffer_rsrc_t rf = rsrc(S.fgeo + (size_t)tile * (3 * FG * 64), 3 * FG * ROW);
         const unsigned vcol4 = (unsigned)col * 4;
-        const int rc0 = bload_i(rn, vcol4, 0), rc1 = bload_i(rn, vcol4, 256), rc2 = bload_i(rn, vcol4, 512);
-        R fd[3 * FG];
+        int rc[3][P];
 #pragma unroll
-        for (int q = 0; q < 3 * FG; ++q) fd[q] = X::load(rf, vcol, q * ROW);
+        for (int f = 0; f < 3; ++f) {
+            const PV<int, P> t = loadp_i<P>(rn, vcol4, f * 256);
+#pragma unroll
+            for (int p = 0; p < P; ++p) rc[f][p] = t.v[p];
+        }
+        R fd[3 * FG][P];
+#pragma unroll
+        for (int q = 0; q < 3 * FG; ++q) {
+            const PV<R, P> t = loadp<R, P>(rf, vcol, q * ROW);
+#pragma unroll
+            for (int p = 0; p < P; ++p) fd[q][p] = t.v[p];
+        }
 
         // ---- volume: derivatives of each field, chain rule and curl into cv
-        R cv[3][MT][4];
+        R cv[3][MT][4][P];
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) cv[f][mt][jj] = R(0);
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) cv[f][mt][jj][p] = R(0);
         // operands of the next field in flight; rows past Np belong to the
         // next field (or lie past the tile, read as 0) and meet zero
         // operator columns
-        R bn[KV];
+        PV<R, P> bn[KV];
 #pragma unroll
-        for (int ks = 0; ks < KV; ++ks) bn[ks] = X::load(rq, vrow, (4 * ks) * ROW);
+        for (int ks = 0; ks < KV; ++ks) bn[ks] = loadp<R, P>(rq, vrow, (4 * ks) * ROW);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            R bq[KV];
+            R bq[KV][P];
 #pragma unroll
-            for (int ks = 0; ks < KV; ++ks) {
-                bq[ks] = bn[ks];
-                if (4 * ks + g < Np) F[(f * Np + 4 * ks + g) * FS + c] = bq[ks];
-            }
+            for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    bq[ks][p] = bn[ks].v[p];
+                    if (4 * ks + g < Np) F[(f * Np + 4 * ks + g) * FS + P * c + p] = bq[ks][p];
+                }
             if (f + 1 < 3) {
 #pragma unroll
-                for (int ks = 0; ks < KV; ++ks) bn[ks] = X::load(rq, vrow, ((f + 1) * Np + 4 * ks) * ROW);
+                for (int ks = 0; ks < KV; ++ks) bn[ks] = loadp<R, P>(rq, vrow, ((f + 1) * Np + 4 * ks) * ROW);
             }
-            V4 d[2][MT];
+            V4 d[P][2][MT];
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) d[p][mt] = V4{R(0), R(0), R(0), R(0)};
+                for (int o = 0; o < 2; ++o)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) d[p][o][mt] = V4{R(0), R(0), R(0), R(0)};
             int la = lane;
             asm volatile("" : "+v"(la));
 #pragma unroll
             for (int ks = 0; ks < KV; ++ks)
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+                for (int o = 0; o < 2; ++o)
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        d[p][mt] = X::mfma(sA[((p * MT + mt) * KV + ks) * 64 + la], bq[ks], d[p][mt]);
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const R a = sA[((o * MT + mt) * KV + ks) * 64 + la];
+#pragma unroll
+                        for (int p = 0; p < P; ++p) d[p][o][mt] = X::mfma(a, bq[ks][p], d[p][o][mt]);
+                    }
             // d_x u = r_x Dr u + s_x Ds u, d_y u = r_y Dr u + s_y Ds u
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const R dr = d[0][mt][jj], ds = d[1][mt][jj];
-                    const R gx = gf[0] * dr + gf[2] * ds;
-                    const R gy = gf[1] * dr + gf[3] * ds;
-                    if (f == 0) cv[2][mt][jj] -= gy;  // Ez: -d_y Hx
-                    if (f == 1) cv[2][mt][jj] += gx;  // Ez: +d_x Hy
-                    if (f == 2) {
-                        cv[0][mt][jj] -= gy;  // Hx: -d_y Ez
-                        cv[1][mt][jj] += gx;  // Hy: +d_x Ez
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const R dr = d[p][0][mt][jj], ds = d[p][1][mt][jj];
+                        const R gx = gf[0][p] * dr + gf[2][p] * ds;
+                        const R gy = gf[1][p] * dr + gf[3][p] * ds;
+                        if (f == 0) cv[2][mt][jj][p] -= gy;  // Ez: -d_y Hx
+                        if (f == 1) cv[2][mt][jj][p] += gx;  // Ez: +d_x Hy
+                        if (f == 2) {
+                            cv[0][mt][jj][p] -= gy;  // Hx: -d_y Ez
+                            cv[1][mt][jj][p] += gx;  // Hy: +d_x Ez
+                        }
                     }
-                }
 #pragma unroll
             for (int o = 0; o < 3; ++o)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) asm volatile("" : "+v"(cv[o][mt][jj]));
+                    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                        for (int p = 0; p < P; ++p) asm volatile("" : "+v"(cv[o][mt][jj][p]));
             __builtin_amdgcn_sched_barrier(0);
         }
 
         // the LIFT contraction accumulates on top of the volume part
-        V4 acc[3][MT];
+        V4 acc[P][3][MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const R im = MAT ? gf[5] : R(1), ie = MAT ? gf[4] : R(1);
-            acc[0][mt] = V4{cv[0][mt][0] * im, cv[0][mt][1] * im, cv[0][mt][2] * im, cv[0][mt][3] * im};
-            acc[1][mt] = V4{cv[1][mt][0] * im, cv[1][mt][1] * im, cv[1][mt][2] * im, cv[1][mt][3] * im};
-            acc[2][mt] = V4{cv[2][mt][0] * ie, cv[2][mt][1] * ie, cv[2][mt][2] * ie, cv[2][mt][3] * ie};
-        }
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const R im = MAT ? gf[5][p] : R(1), ie = MAT ? gf[4][p] : R(1);
+                acc[p][0][mt] = V4{cv[0][mt][0][p] * im, cv[0][mt][1][p] * im, cv[0][mt][2][p] * im, cv[0][mt][3][p] * im};
+                acc[p][1][mt] = V4{cv[1][mt][0][p] * im, cv[1][mt][1][p] * im, cv[1][mt][2][p] * im, cv[1][mt][3][p] * im};
+                acc[p][2][mt] = V4{cv[2][mt][0][p] * ie, cv[2][mt][1][p] * ie, cv[2][mt][2][p] * ie, cv[2][mt][3][p] * ie};
+            }
 
         // ---- surface: flux at face node j = 4 ks + g, then LIFT
-        auto face_rec = [&](int face) { return face == 0 ? rc0 : (face == 1 ? rc1 : rc2); };
-        auto face_val = [&](int face, int q) { return face == 0 ? fd[q] : (face == 1 ? fd[FG + q] : fd[2 * FG + q]); };
-        // own and partner traces of face node j (on the wall the partner is
-        // the element itself; the mirror sign is applied with the jump)
-        auto load_traces = [&](int ks, R (&m)[3], R (&pv)[3], int &wall) {
+        // The four face nodes 4 ks .. 4 ks + 3 of a K-step lie on at most two
+        // faces, lo and hi (fixed once the loop over ks is unrolled): a
+        // two-way select per value, with constant array indices (a select
+        // over all three faces becomes an indexed scratch-memory lookup).
+        auto face_lo = [](int ks) { return (4 * ks < Nafp ? 4 * ks : Nafp - 1) / Nfp; };
+        auto face_hi = [](int ks) { return (4 * ks + 3 < Nafp ? 4 * ks + 3 : Nafp - 1) / Nfp; };
+        auto face_rec = [&](int ks, bool hi, int p) { return hi ? rc[face_hi(ks)][p] : rc[face_lo(ks)][p]; };
+        auto face_val = [&](int ks, bool hi, int q, int p) {
+            return hi ? fd[face_hi(ks) * FG + q][p] : fd[face_lo(ks) * FG + q][p];
+        };
+        // own and partner traces of face node j for element p of the lane
+        // (on the wall the partner is the element itself; the mirror sign is
+        // applied with the jump)
+        auto load_traces = [&](int ks, R (&m)[3][P], R (&pv)[3][P], int (&wall)[P]) {
             const int j = 4 * ks + g;
             const int jc = j < Nafp ? j : Nafp - 1;  // lanes past the faces read a valid node
             const int face = jc / Nfp, i = jc - face * Nfp;
+            const bool hi = face > face_lo(ks);
             const int own = stab[jc];
-            const int rc = face_rec(face);
-            wall = rc < 0;
-            const int e2 = wall ? tile * 64 + col : (rc >> 5);
-            const int pn = wall ? own : stab[Nafp + (((rc >> 3) & 3) * 2 + (rc & 7)) * Nfp + i];
-            const R *qp = X::qin(A) + tix(e2, pn, 3 * Np);
 #pragma unroll
-            for (int f = 0; f < 3; ++f) m[f] = F[(f * Np + own) * FS + c];
+            for (int p = 0; p < P; ++p) {
+                const int rcv = face_rec(ks, hi, p);
+                wall[p] = rcv < 0;
+                const int e2 = wall[p] ? tile * 64 + col + p : (rcv >> 5);
+                const int pn = wall[p] ? own : stab[Nafp + (((rcv >> 3) & 3) * 2 + (rcv & 7)) * Nfp + i];
+                const R *qp = S.qin + tix(e2, pn, 3 * Np);
 #pragma unroll
-            for (int f = 0; f < 3; ++f) pv[f] = qp[(size_t)f * Np * 64];
+                for (int f = 0; f < 3; ++f) m[f][p] = F[(f * Np + own) * FS + P * c + p];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) pv[f][p] = qp[(size_t)f * Np * 64];
+            }
         };
         constexpr int SPD = 2;  // K-steps of traces in flight
-        R mb[SPD][3], pb[SPD][3];
-        int wb[SPD];
+        R mb[SPD][3][P], pb[SPD][3][P];
+        int wb[SPD][P];
 #pragma unroll
         for (int s0 = 0; s0 < SPD; ++s0)
             if (s0 < KL) load_traces(s0, mb[s0], pb[s0], wb[s0]);
 #pragma unroll
         for (int ks = 0; ks < KL; ++ks) {
-            R m[3], pv[3];
+            R m[3][P], pv[3][P];
+            int wall[P];
             const int slot = ks % SPD;
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                m[f] = mb[slot][f];
-                pv[f] = pb[slot][f];
+            for (int p = 0; p < P; ++p) {
+                wall[p] = wb[slot][p];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    m[f][p] = mb[slot][f][p];
+                    pv[f][p] = pb[slot][f][p];
+                }
             }
-            const int wall = wb[slot];
             if (ks + SPD < KL) load_traces(ks + SPD, mb[slot], pb[slot], wb[slot]);
             const int j = 4 * ks + g;
-            const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
-            // [q] = q- - q+, with q+ = (H-, -E-) on the wall
-            const R dHx = m[0] - pv[0], dHy = m[1] - pv[1];
-            const R dEz = m[2] - (wall ? -pv[2] : pv[2]);
-            const R nx = face_val(face, 0), ny = face_val(face, 1);
-            const R dh = nx * dHy - ny * dHx;  // jump of the tangential field
-            R cEE, cEh, cHE, cHh;
-            if (MAT) {
-                cEE = face_val(face, 2);
-                cEh = face_val(face, 3);
-                cHE = face_val(face, 4);
-                cHh = face_val(face, 5);
-            } else {
-                const R fs = face_val(face, 2);
-                cEE = hs_alpha * fs;
-                cEh = R(0.5) * fs;
-                cHE = R(0.5) * fs;
-                cHh = hs_alpha * fs;
-            }
+            const bool hi = (j < Nafp ? j : Nafp - 1) / Nfp > face_lo(ks);
             const R on = j < Nafp ? R(1) : R(0);  // lanes past the faces feed zero rows
-            const R fE = -(cEE * dEz + cEh * dh) * on;
-            const R fH = (cHE * dEz + cHh * dh) * on;
-            const R fl[3] = {ny * fH, -nx * fH, fE};
+            R fl[3][P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                // [q] = q- - q+, with q+ = (H-, -E-) on the wall
+                const R dHx = m[0][p] - pv[0][p], dHy = m[1][p] - pv[1][p];
+                const R dEz = m[2][p] - (wall[p] ? -pv[2][p] : pv[2][p]);
+                const R nx = face_val(ks, hi, 0, p), ny = face_val(ks, hi, 1, p);
+                const R dh = nx * dHy - ny * dHx;  // jump of the tangential field
+                R cEE, cEh, cHE, cHh;
+                if (MAT) {
+                    cEE = face_val(ks, hi, 2, p);
+                    cEh = face_val(ks, hi, 3, p);
+                    cHE = face_val(ks, hi, 4, p);
+                    cHh = face_val(ks, hi, 5, p);
+                } else {
+                    const R fs = face_val(ks, hi, 2, p);
+                    cEE = hs_alpha * fs;
+                    cEh = R(0.5) * fs;
+                    cHE = R(0.5) * fs;
+                    cHh = hs_alpha * fs;
+                }
+                const R fE = -(cEE * dEz + cEh * dh) * on;
+                const R fH = (cHE * dEz + cHh * dh) * on;
+                fl[0][p] = ny * fH;
+                fl[1][p] = -nx * fH;
+                fl[2][p] = fE;
+            }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 const R a = sA[AV + (mt * KL + ks) * 64 + lane];
 #pragma unroll
-                for (int f = 0; f < 3; ++f) acc[f][mt] = X::mfma(a, fl[f], acc[f][mt]);
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) acc[p][f][mt] = X::mfma(a, fl[f][p], acc[p][f][mt]);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -337,37 +462,40 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT>::WPB)) stage2d_df_kernel
         // then the stores.  Value jj of M-tile mt is node
         // 16 mt + RG g + RJ jj; rows >= Np are not stored.
         constexpr int RG = X::RG, RJ = X::RJ;
-        const __amdgpu_buffer_rsrc_t rr = rsrc(X::res(A) + (size_t)tile * (3 * Np * 64), TB);
-        const __amdgpu_buffer_rsrc_t ro = rsrc(X::qout(A) + (size_t)tile * (3 * Np * 64), TB);
+        const __amdgpu_buffer_rsrc_t rr = rsrc(S.res + (size_t)tile * (3 * Np * 64), TB);
+        const __amdgpu_buffer_rsrc_t ro = rsrc(S.qout + (size_t)tile * (3 * Np * 64), TB);
         const unsigned vout = (unsigned)(RG * g * 64 + col) * W;  // row RG g of column col
-        const R ca = X::a(A), cb = X::b(A), cdt = X::dt(A);
+        const R ca = X::a(A), cb = X::b(A), cdt = S.dt;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            R rv[MT][4], qv[MT][4];
+            PV<R, P> rv[MT][4], qv[MT][4];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const unsigned so = (f * Np + 16 * mt + RJ * jj) * ROW;
-                    rv[mt][jj] = X::load(rr, vout, so);
+                    rv[mt][jj] = loadp<R, P>(rr, vout, so);
                     const int n = 16 * mt + RG * g + RJ * jj;
-                    qv[mt][jj] = n < Np ? F[(f * Np + n) * FS + c] : R(0);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) qv[mt][jj].v[p] = n < Np ? F[(f * Np + n) * FS + P * c + p] : R(0);
                 }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    rv[mt][jj] = ca * rv[mt][jj] + cdt * acc[f][mt][jj];
-                    qv[mt][jj] = qv[mt][jj] + cb * rv[mt][jj];
-                }
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        rv[mt][jj].v[p] = ca * rv[mt][jj].v[p] + cdt * acc[p][f][mt][jj];
+                        qv[mt][jj].v[p] = qv[mt][jj].v[p] + cb * rv[mt][jj].v[p];
+                    }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     if (16 * mt + RG * g + RJ * jj < Np) {
                         const unsigned so = (f * Np + 16 * mt + RJ * jj) * ROW;
-                        X::store(rr, rv[mt][jj], vout, so);
-                        X::store(ro, qv[mt][jj], vout, so);
+                        storep<R, P>(rr, rv[mt][jj], vout, so);
+                        storep<R, P>(ro, qv[mt][jj], vout, so);
                     }
                 }
         }
@@ -376,22 +504,33 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT>::WPB)) stage2d_df_kernel
 
 namespace {
 
-template <typename R, int N, bool MAT>
+// element pairs per lane in the FP32 kernel
+#ifndef DGW_DF_FP32_PAIRS
+#define DGW_DF_FP32_PAIRS 0
+#endif
+template <typename R>
+constexpr int kPairs = (sizeof(R) == 4 && DGW_DF_FP32_PAIRS) ? 2 : 1;
+
+template <typename R, int N, bool MAT, bool BATCH = false>
 hipError_t launch_df(const StageArgs &a, hipStream_t s) {
+    constexpr int P = kPairs<R>;
     using X = Arith<R>;
     // every pointer the kernel dereferences must be set
-    if (!X::frag(a) || !a.itab || !X::qin(a) || !X::qout(a) || !X::res(a) || !X::geo(a) || !X::fgeo(a) || !a.nbr ||
-        a.ntiles <= 0 || a.ngroups < 8 || (a.ngroups & 7))
+    const bool bufs = BATCH ? (a.batch && a.tile_req)
+                            : (X::qin(a) && X::qout(a) && X::res(a) && X::geo(a) && X::fgeo(a) && a.nbr);
+    if (!X::frag(a) || !a.itab || !bufs || a.ntiles <= 0 || a.ngroups < 8 || (a.ngroups & 7))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage2d_df_kernel<R, N, MAT>), dim3(a.ngroups), dim3(64 * TriD<R, N, MAT>::WPB), 0, s, a);
+    hipLaunchKernelGGL((stage2d_df_kernel<R, N, MAT, P, BATCH>), dim3(a.ngroups),
+                       dim3(64 * TriD<R, N, MAT, P>::WPB), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename R, int N, bool MAT>
+template <typename R, int N, bool MAT, bool BATCH = false>
 int occupancy_df() {
+    constexpr int P = kPairs<R>;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_df_kernel<R, N, MAT>, 64 * TriD<R, N, MAT>::WPB,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_df_kernel<R, N, MAT, P, BATCH>,
+                                                     64 * TriD<R, N, MAT, P>::WPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -441,6 +580,27 @@ int blocks_per_cu_2d_df(int N, bool material, bool fp64) {
     case n:                                                                                          \
         if (fp64) return material ? occupancy_df<double, n, true>() : occupancy_df<double, n, false>(); \
         return material ? occupancy_df<float, n, true>() : occupancy_df<float, n, false>();
+        DGW_ORDERS(DGW_CASE)
+#undef DGW_CASE
+        default: return 1;
+    }
+}
+
+// Batched FP32 launches (a.batch, a.tile_req, a.parity; a.ntiles = total tiles)
+hipError_t launch_stage2d_df_batch(int N, bool material, const StageArgs &a, hipStream_t s) {
+    switch (N) {
+#define DGW_CASE(n) \
+    case n: return material ? launch_df<float, n, true, true>(a, s) : launch_df<float, n, false, true>(a, s);
+        DGW_ORDERS(DGW_CASE)
+#undef DGW_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int blocks_per_cu_2d_df_batch(int N, bool material) {
+    switch (N) {
+#define DGW_CASE(n) \
+    case n: return material ? occupancy_df<float, n, true, true>() : occupancy_df<float, n, false, true>();
         DGW_ORDERS(DGW_CASE)
 #undef DGW_CASE
         default: return 1;

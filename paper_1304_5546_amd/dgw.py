@@ -46,7 +46,8 @@ class Opts(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("steps", C.c_int64), ("dt", C.c_double), ("t", C.c_double), ("setup_s", C.c_double),
-                ("solve_ms", C.c_double), ("dof_updates_per_s", C.c_double)]
+                ("solve_ms", C.c_double), ("dof_updates_per_s", C.c_double), ("kernel", C.c_int32),
+                ("groups_per_cu", C.c_int32)]
 
 
 TUNE_MAX = 16
