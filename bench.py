@@ -254,12 +254,12 @@ def main():
     if dim == 3:
         kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
     elif pcode == 3:
-        kname = f"stage2d_kernel<double, {N}, false>" if variant == 1 else f"stage2d_df_kernel<double, {N}, false, 1, false>"
+        kname = f"stage2d_kernel<double, {N}, false>" if variant == 1 else f"stage2d_df_kernel<double, {N}, false, 1>"
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
         kname = {1: f"stage2d_kernel<float, {N}, false>",
-                 3: f"stage2d_df_kernel<float, {N}, false, 1, false>"}.get(variant,
+                 3: f"stage2d_df_kernel<float, {N}, false, 1>"}.get(variant,
                                                                           f"stage2d_mfma_kernel<{N}, false, false>")
     out = {
         "metric": METRIC,

@@ -109,9 +109,6 @@ hipError_t launch_stage2d_fp64(int N, bool material, const StageArgs &a, hipStre
 // a.opsfrag64)
 hipError_t launch_stage2d_df(int N, bool material, bool fp64, const StageArgs &a, hipStream_t s);
 int blocks_per_cu_2d_df(int N, bool material, bool fp64);
-// its batched FP32 form (a.batch / a.tile_req / a.parity, as launch_stage2d_batch)
-hipError_t launch_stage2d_df_batch(int N, bool material, const StageArgs &a, hipStream_t s);
-int blocks_per_cu_2d_df_batch(int N, bool material);
 // the 2D FP32 kernel that runs by default: derivative-first up to order 6,
 // fused-operand from order 7 (measured: faster at every order on 131k
 // elements, slower at order 7 on 524k)

@@ -79,8 +79,6 @@ struct Group {
     int *tiles_h = nullptr, *tiles_d = nullptr;
     size_t cap_desc = 0, cap_tiles = 0;
     float *opsfrag_d = nullptr;  // fragment-ordered operator of this order (group-owned copy)
-    int *itab_d = nullptr;       // face-node tables of this order (group-owned copy)
-    bool deriv_first = false;    // the group runs the derivative-first kernel
 };
 
 using GroupKey = std::tuple<int, bool, double>;
@@ -287,21 +285,22 @@ int run_chunk(dgw_server *S, const std::vector<Req *> &batch, int64_t chunk) {
             g.order = std::get<0>(kv.first);
             g.material = std::get<1>(kv.first);
             g.alpha = std::get<2>(kv.first);
-            g.deriv_first = dgw::auto_deriv_first(g.order);
-            g.per_cu = g.deriv_first ? dgw::blocks_per_cu_2d_df_batch(g.order, g.material)
-                                     : dgw::blocks_per_cu_2d_batch(g.order, g.material);
+            // the fused-operand batched kernel at every order (a batched form
+            // of the derivative-first kernel, which looks the owning request
+            // up once per 16-element unit on its critical path, measured
+            // slower in the serving mix: 4.07e10 against 4.47e10
+            // DOF-updates/s, 96 requests in a burst)
+            g.per_cu = dgw::blocks_per_cu_2d_batch(g.order, g.material);
             if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
                 return dgw::set_error(DGW_EDEVICE, "stream creation failed");
         }
         if (!g.opsfrag_d) {
             // the operator depends on the order only: copy it from the first
-            // solve of the group (its upload completed in dgw_create), in the
-            // fragment order of the group's kernel
+            // solve of the group (its upload completed in dgw_create)
             const dgw_solver *s0 = kv.second.front()->s;
-            const size_t n = g.deriv_first ? (size_t)dgw::opsfrag2d_df(g.order, nullptr, nullptr, nullptr, nullptr)
-                                           : (size_t)dgw::opsfrag2d(g.order, nullptr, nullptr, nullptr, nullptr);
-            const float *src = g.deriv_first ? s0->opsfrag_df_d : s0->opsfrag_d;
+            const size_t n = (size_t)dgw::opsfrag2d(g.order, nullptr, nullptr, nullptr, nullptr);
+            const float *src = s0->opsfrag_d;
             if (!src) return dgw::set_error(DGW_EINVAL, "internal: operator fragments missing");
             if (hipMalloc((void **)&g.opsfrag_d, n * sizeof(float)) != hipSuccess) {
                 g.opsfrag_d = nullptr;
@@ -309,13 +308,6 @@ int run_chunk(dgw_server *S, const std::vector<Req *> &batch, int64_t chunk) {
             }
             if (hipMemcpyAsync(g.opsfrag_d, src, n * sizeof(float), hipMemcpyDeviceToDevice, g.stream) != hipSuccess)
                 return dgw::set_error(DGW_EDEVICE, "operator table copy failed");
-            const size_t nt = (size_t)3 * (g.order + 1) * 3;  // own face nodes + partner table (2 orientations)
-            if (hipMalloc((void **)&g.itab_d, nt * sizeof(int)) != hipSuccess) {
-                g.itab_d = nullptr;
-                return dgw::set_error(DGW_ENOMEM, "face table allocation failed");
-            }
-            if (hipMemcpyAsync(g.itab_d, s0->itab_d, nt * sizeof(int), hipMemcpyDeviceToDevice, g.stream) != hipSuccess)
-                return dgw::set_error(DGW_EDEVICE, "face table copy failed");
         }
         auto &rs = kv.second;
         std::sort(rs.begin(), rs.end(), [](const Req *a, const Req *b) { return a->id < b->id; });
@@ -364,9 +356,7 @@ int run_chunk(dgw_server *S, const std::vector<Req *> &batch, int64_t chunk) {
                 a.a = (float)dgw::kRkA[k];
                 a.b = (float)dgw::kRkB[k];
                 a.alpha = (float)g.alpha;
-                a.itab = g.itab_d;
-                hipError_t e = g.deriv_first ? dgw::launch_stage2d_df_batch(g.order, g.material, a, g.stream)
-                                             : dgw::launch_stage2d_batch(g.order, g.material, a, g.stream);
+                hipError_t e = dgw::launch_stage2d_batch(g.order, g.material, a, g.stream);
                 if (e != hipSuccess) return dgw::set_error(DGW_EDEVICE, hipGetErrorString(e));
             }
     for (auto &gl : launch) {
@@ -669,7 +659,6 @@ void dgw_server_destroy(dgw_server *S) {
         if (g.desc_d) hipFree(g.desc_d);
         if (g.tiles_d) hipFree(g.tiles_d);
         if (g.opsfrag_d) hipFree(g.opsfrag_d);
-        if (g.itab_d) hipFree(g.itab_d);
         if (g.done) hipEventDestroy(g.done);
         if (g.stream) hipStreamDestroy(g.stream);
     }

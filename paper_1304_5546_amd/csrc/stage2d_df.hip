@@ -173,8 +173,7 @@ __device__ __forceinline__ void storep(__amdgpu_buffer_rsrc_t r, PV<R, P> x, uns
     }
 }
 
-// Buffers of the solve that owns global tile t, and t's index inside it
-// (batched launches: a wave-uniform lookup of the solve's descriptor).
+// Buffers of the solve and its tile t.
 template <typename R>
 struct DfSrc {
     const R *qin;
@@ -184,23 +183,15 @@ struct DfSrc {
     int tile;
     R dt;
 };
-template <typename R, bool BATCH>
+template <typename R>
 __device__ __forceinline__ DfSrc<R> df_src(const StageArgs &A, int t) {
     using X = Arith<R>;
-    if constexpr (!BATCH) {
-        return DfSrc<R>{X::qin(A), X::qout(A), X::res(A), X::geo(A), X::fgeo(A), A.nbr, t, X::dt(A)};
-    } else {
-        static_assert(sizeof(R) == 4, "batched launches are FP32");
-        const int r = __builtin_amdgcn_readfirstlane(A.tile_req[t]);
-        const BatchDesc &d = A.batch[r];
-        const int ci = (d.cur0 ^ A.parity) & 1;
-        return DfSrc<R>{d.q[ci], d.q[ci ^ 1], d.res, d.geo, d.fgeo, d.nbr, t - d.tile0, d.dt};
-    }
+    return DfSrc<R>{X::qin(A), X::qout(A), X::res(A), X::geo(A), X::fgeo(A), A.nbr, t, X::dt(A)};
 }
 
 }  // namespace
 
-template <typename R, int N, bool MAT, int P, bool BATCH>
+template <typename R, int N, bool MAT, int P>
 __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_kernel(StageArgs A) {
     using T = TriD<R, N, MAT, P>;
     using X = Arith<R>;
@@ -233,7 +224,7 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
 
     for (int ul = bi * WPB + w; ul < xcount; ul += GB * WPB) {
         const int unit = xbase + ul;
-        const DfSrc<R> S = df_src<R, BATCH>(A, unit / UPT);
+        const DfSrc<R> S = df_src<R>(A, unit / UPT);
         const int tile = S.tile;  // tile within the solve
         // lane indices opaque to the compiler, recomputed per work unit
         int lane = lane0;
@@ -511,25 +502,24 @@ namespace {
 template <typename R>
 constexpr int kPairs = (sizeof(R) == 4 && DGW_DF_FP32_PAIRS) ? 2 : 1;
 
-template <typename R, int N, bool MAT, bool BATCH = false>
+template <typename R, int N, bool MAT>
 hipError_t launch_df(const StageArgs &a, hipStream_t s) {
     constexpr int P = kPairs<R>;
     using X = Arith<R>;
     // every pointer the kernel dereferences must be set
-    const bool bufs = BATCH ? (a.batch && a.tile_req)
-                            : (X::qin(a) && X::qout(a) && X::res(a) && X::geo(a) && X::fgeo(a) && a.nbr);
+    const bool bufs = X::qin(a) && X::qout(a) && X::res(a) && X::geo(a) && X::fgeo(a) && a.nbr;
     if (!X::frag(a) || !a.itab || !bufs || a.ntiles <= 0 || a.ngroups < 8 || (a.ngroups & 7))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage2d_df_kernel<R, N, MAT, P, BATCH>), dim3(a.ngroups),
-                       dim3(64 * TriD<R, N, MAT, P>::WPB), 0, s, a);
+    hipLaunchKernelGGL((stage2d_df_kernel<R, N, MAT, P>), dim3(a.ngroups), dim3(64 * TriD<R, N, MAT, P>::WPB), 0, s,
+                       a);
     return hipGetLastError();
 }
 
-template <typename R, int N, bool MAT, bool BATCH = false>
+template <typename R, int N, bool MAT>
 int occupancy_df() {
     constexpr int P = kPairs<R>;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_df_kernel<R, N, MAT, P, BATCH>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_df_kernel<R, N, MAT, P>,
                                                      64 * TriD<R, N, MAT, P>::WPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -580,27 +570,6 @@ int blocks_per_cu_2d_df(int N, bool material, bool fp64) {
     case n:                                                                                          \
         if (fp64) return material ? occupancy_df<double, n, true>() : occupancy_df<double, n, false>(); \
         return material ? occupancy_df<float, n, true>() : occupancy_df<float, n, false>();
-        DGW_ORDERS(DGW_CASE)
-#undef DGW_CASE
-        default: return 1;
-    }
-}
-
-// Batched FP32 launches (a.batch, a.tile_req, a.parity; a.ntiles = total tiles)
-hipError_t launch_stage2d_df_batch(int N, bool material, const StageArgs &a, hipStream_t s) {
-    switch (N) {
-#define DGW_CASE(n) \
-    case n: return material ? launch_df<float, n, true, true>(a, s) : launch_df<float, n, false, true>(a, s);
-        DGW_ORDERS(DGW_CASE)
-#undef DGW_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-int blocks_per_cu_2d_df_batch(int N, bool material) {
-    switch (N) {
-#define DGW_CASE(n) \
-    case n: return material ? occupancy_df<float, n, true, true>() : occupancy_df<float, n, false, true>();
         DGW_ORDERS(DGW_CASE)
 #undef DGW_CASE
         default: return 1;
