@@ -523,7 +523,7 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     // the kernel that runs: 2D FP32 auto = derivative-first up to order 6,
     // fused-operand MFMA above; FP64 auto = derivative-first; split and 3D
     // have one kernel each
-    const bool plain32 = opts.prec == DGW_FP32 && s->dim == 2;
+    const bool plain32 = opts.prec == DGW_FP32 && mesh->dim == 2;
     s->variant = opts.kernel == dgw::kVariantAuto
                      ? (s->fp64 || (plain32 && dgw::auto_deriv_first(order)) ? dgw::kVariantDerivFirst
                                                                              : dgw::kVariantMfma)

@@ -142,6 +142,10 @@ def test_error_paths_before_any_device_call():
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="split_fp16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec="split_fp16", kernel=1, device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec=7, device=-1))
+    # kernel variants: 3 is a 2D FP32/FP64 kernel, split runs its own kernels
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=4, device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=3, prec="split_bf16", device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, kernel=3, device=-1))
     # the FP64 field path is 2D only
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="fp64", device=-1))
     dgw.Solver(m, 3, prec="fp64", kernel=1, device=-1).close()
@@ -172,3 +176,20 @@ def test_footprint_is_host_only_and_scales():
     f64 = dgw.footprint(m, 5, prec="fp64")
     assert f64 - dgw.footprint(m, 5, prec="split_bf16") > 3 * 3 * 21 * Kp * 4
     _expect("DGW_EORDER", lambda: dgw.footprint(m, 9))
+
+
+def test_kernel_choice_is_resolved_at_create():
+    """opts.kernel = 0 resolves to the derivative-first kernel (3) for FP32
+    up to order 6 and for FP64, to the fused-operand kernel (2) from order
+    7 and for the split and 3D paths; an explicit choice is kept (FP64 maps
+    the matrix-core request 2 to its only matrix-core kernel, 3)."""
+    m = inputs.tri_grid(4, seed=1)
+    t = inputs.tet_grid(1)
+    cases = [(m, 5, "fp32", 0, 3), (m, 6, "fp32", 0, 3), (m, 7, "fp32", 0, 2), (m, 8, "fp32", 0, 2),
+             (m, 5, "fp64", 0, 3), (m, 5, "fp64", 2, 3), (m, 5, "fp64", 1, 1), (m, 5, "split_bf16", 0, 2),
+             (m, 5, "fp32", 2, 2), (m, 5, "fp32", 1, 1), (t, 2, "fp32", 0, 2)]
+    for mesh, N, prec, k, want in cases:
+        with dgw.Solver(mesh, N, prec=prec, kernel=k, device=-1) as s:
+            info = s.info()
+            assert info["kernel"] == want, (N, prec, k, info["kernel"])
+            assert info["groups_per_cu"] == 0  # no device: no launch shape yet
