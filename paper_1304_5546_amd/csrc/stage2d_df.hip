@@ -191,6 +191,11 @@ __device__ __forceinline__ DfSrc<R> df_src(const StageArgs &A, int t) {
 
 }  // namespace
 
+// Tuning: K-steps of face traces kept in flight.
+#ifndef DGW_DF_SPD
+#define DGW_DF_SPD 2
+#endif
+
 template <typename R, int N, bool MAT, int P>
 __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_kernel(StageArgs A) {
     using T = TriD<R, N, MAT, P>;
@@ -386,7 +391,7 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
                 for (int f = 0; f < 3; ++f) pv[f][p] = qp[(size_t)f * Np * 64];
             }
         };
-        constexpr int SPD = 2;  // K-steps of traces in flight
+        constexpr int SPD = DGW_DF_SPD;  // K-steps of traces in flight
         R mb[SPD][3][P], pb[SPD][3][P];
         int wb[SPD][P];
 #pragma unroll
