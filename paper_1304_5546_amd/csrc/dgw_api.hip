@@ -861,25 +861,29 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     int best = -1;
     double best_us = 0;
     const double dt = s->dt_cfl;
-    for (size_t i = 0; i < cand.size(); ++i) {
+    // a failing step ends the search; the state is restored either way
+    auto try_hip = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && !rc) rc = fail(DGW_EDEVICE, std::string("autotune: ") + what + ": " + hipGetErrorString(e));
+        return rc == DGW_OK;
+    };
+    for (size_t i = 0; i < cand.size() && rc == DGW_OK; ++i) {
         s->variant = cand[i].first;
         set_grid(s, cand[i].second);
         dgw::StageArgs a = stage_args(s);
-        auto run = [&](int n) -> int {
-            for (int k = 0; k < n; ++k) {
+        auto run = [&](int n) {
+            for (int k = 0; k < n && rc == DGW_OK; ++k) {
                 set_stage(s, a, kRkA[k % 5], kRkB[k % 5], dt);
-                DGW_HIP(launch_one(s, a, s->stream));
+                try_hip(launch_one(s, a, s->stream), "stage launch");
                 s->cur = 1 - s->cur;
             }
-            return DGW_OK;
+            return rc == DGW_OK;
         };
-        if ((rc = run(2))) break;
-        DGW_HIP(hipEventRecord(s->ev0, s->stream));
-        if ((rc = run(stages))) break;
-        DGW_HIP(hipEventRecord(s->ev1, s->stream));
-        DGW_HIP(hipEventSynchronize(s->ev1));
         float ms = 0;
-        DGW_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+        if (!run(2) || !try_hip(hipEventRecord(s->ev0, s->stream), "event") || !run(stages) ||
+            !try_hip(hipEventRecord(s->ev1, s->stream), "event") ||
+            !try_hip(hipEventSynchronize(s->ev1), "event synchronisation") ||
+            !try_hip(hipEventElapsedTime(&ms, s->ev0, s->ev1), "event timing"))
+            break;
         const double us = 1e3 * ms / stages;
         info.tried_kernel[i] = cand[i].first;
         info.tried_groups_per_cu[i] = cand[i].second;
@@ -893,9 +897,9 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     // restore the state, keep the fastest candidate (or the old choice on error)
     s->cur = cur0;
     cur_d = s->fp64 ? (void *)s->q64[s->cur] : (void *)s->q[s->cur];
-    DGW_HIP(hipMemcpyAsync(cur_d, save, bytes, hipMemcpyDeviceToDevice, s->stream));
-    DGW_HIP(hipMemcpyAsync(res_d, (char *)save + bytes, bytes, hipMemcpyDeviceToDevice, s->stream));
-    DGW_HIP(hipStreamSynchronize(s->stream));
+    try_hip(hipMemcpyAsync(cur_d, save, bytes, hipMemcpyDeviceToDevice, s->stream), "state restore");
+    try_hip(hipMemcpyAsync(res_d, (char *)save + bytes, bytes, hipMemcpyDeviceToDevice, s->stream), "state restore");
+    try_hip(hipStreamSynchronize(s->stream), "synchronisation");
     if (rc || best < 0) {
         s->variant = var0;
         set_grid(s, gpc0);
