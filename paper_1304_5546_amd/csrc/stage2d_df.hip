@@ -191,9 +191,13 @@ __device__ __forceinline__ DfSrc<R> df_src(const StageArgs &A, int t) {
 
 }  // namespace
 
-// Tuning: K-steps of face traces kept in flight.
+// Tuning: K-steps of face traces kept in flight; fields whose residual rows
+// are loaded before the surface loop.
 #ifndef DGW_DF_SPD
 #define DGW_DF_SPD 2
+#endif
+#ifndef DGW_DF_RPF
+#define DGW_DF_RPF 1
 #endif
 
 template <typename R, int N, bool MAT, int P>
@@ -358,6 +362,23 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
                 acc[p][2][mt] = V4{cv[2][mt][0][p] * ie, cv[2][mt][1][p] * ie, cv[2][mt][2][p] * ie, cv[2][mt][3][p] * ie};
             }
 
+        // residual rows of the first RPF fields, issued before the surface
+        // loop so that their latency overlaps it (pinned there by the
+        // scheduling barrier)
+        constexpr int RPF = DGW_DF_RPF;
+        constexpr int RG = X::RG, RJ = X::RJ;
+        const __amdgpu_buffer_rsrc_t rr = rsrc(S.res + (size_t)tile * (3 * Np * 64), TB);
+        const unsigned vout = (unsigned)(RG * g * 64 + col) * W;  // row RG g of column col
+        PV<R, P> rpre[RPF > 0 ? RPF : 1][MT][4];
+#pragma unroll
+        for (int f = 0; f < RPF; ++f)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    rpre[f][mt][jj] = loadp<R, P>(rr, vout, (f * Np + 16 * mt + RJ * jj) * ROW);
+        __builtin_amdgcn_sched_barrier(0);
+
         // ---- surface: flux at face node j = 4 ks + g, then LIFT
         // The four face nodes 4 ks .. 4 ks + 3 of a K-step lie on at most two
         // faces, lo and hi (fixed once the loop over ks is unrolled): a
@@ -457,10 +478,7 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
         // q_out <- q_in + b res; per field all loads, then the arithmetic,
         // then the stores.  Value jj of M-tile mt is node
         // 16 mt + RG g + RJ jj; rows >= Np are not stored.
-        constexpr int RG = X::RG, RJ = X::RJ;
-        const __amdgpu_buffer_rsrc_t rr = rsrc(S.res + (size_t)tile * (3 * Np * 64), TB);
         const __amdgpu_buffer_rsrc_t ro = rsrc(S.qout + (size_t)tile * (3 * Np * 64), TB);
-        const unsigned vout = (unsigned)(RG * g * 64 + col) * W;  // row RG g of column col
         const R ca = X::a(A), cb = X::b(A), cdt = S.dt;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -470,7 +488,7 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const unsigned so = (f * Np + 16 * mt + RJ * jj) * ROW;
-                    rv[mt][jj] = loadp<R, P>(rr, vout, so);
+                    rv[mt][jj] = f < RPF ? rpre[f < RPF ? f : 0][mt][jj] : loadp<R, P>(rr, vout, so);
                     const int n = 16 * mt + RG * g + RJ * jj;
 #pragma unroll
                     for (int p = 0; p < P; ++p) qv[mt][jj].v[p] = n < Np ? F[(f * Np + n) * FS + P * c + p] : R(0);
