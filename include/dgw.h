@@ -147,7 +147,10 @@ typedef struct {
 
 /* Set up the discretisation of order `order` on `mesh` (host FP64), upload
  * operators and geometry, allocate the fields (zero).  Errors: EINVAL,
- * EMESH, EORDER, ENOMEM, EDEVICE. */
+ * EMESH, EORDER, ENOMEM, EDEVICE; ETOOBIG for 2^26 elements or more, for a
+ * 2D field array of 2^32 values or more (n_fields * Np * K rounded up to 64
+ * elements; partner traces are addressed by 32-bit element indices) and for
+ * a 3D field array of 2 GiB or more (32-bit byte offsets). */
 int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts, dgw_solver **out);
 void dgw_destroy(dgw_solver *s);
 

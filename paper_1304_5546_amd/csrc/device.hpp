@@ -34,6 +34,14 @@ __host__ __device__ inline size_t tix(int64_t e, int row, int rows) {
     return ((size_t)(e >> 6) * rows + row) * 64 + (size_t)(e & 63);
 }
 
+// The 2D fused-operand and split kernels address partner traces by 32-bit
+// element indices into the [tile][3 Np][64] field array: true when the array
+// of a 2D solve of order N on K elements stays below 2^32 values.
+inline bool fits_index32_2d(int N, int64_t K) {
+    const int64_t Np = (int64_t)(N + 1) * (N + 2) / 2, Kp = (K + 63) / 64 * 64;
+    return 3 * Np * Kp < (int64_t(1) << 32);
+}
+
 // One solve inside a batched stage launch: its buffers, its first tile in
 // the launch's global tile numbering, and its time step.
 struct BatchDesc {

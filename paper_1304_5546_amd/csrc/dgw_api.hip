@@ -502,6 +502,8 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if (order < 1 || order > (mesh->dim == 2 ? 8 : 4))
         return fail(DGW_EORDER, "order must be in 1..8 (2D) or 1..4 (3D)");
     if (mesh->n_elems >= (int64_t(1) << 26)) return fail(DGW_ETOOBIG, "more than 2^26 elements");
+    if (mesh->dim == 2 && !dgw::fits_index32_2d(order, mesh->n_elems))
+        return fail(DGW_ETOOBIG, "2D field arrays are limited to 2^32 values (32-bit partner-trace indices)");
     dgw_opts opts;
     dgw_opts_default(&opts);
     if (opts_in) opts = *opts_in;

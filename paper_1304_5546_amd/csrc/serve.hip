@@ -509,6 +509,8 @@ int dgw_submit(dgw_server *S, const dgw_request *q, uint64_t *ticket) {
         return dgw::set_error(DGW_EINVAL, "empty mesh or NULL mesh array");
     if (m.n_elems >= (int64_t(1) << 26)) return dgw::set_error(DGW_ETOOBIG, "more than 2^26 elements");
     if (q->order < 1 || q->order > 8) return dgw::set_error(DGW_EORDER, "order must be in 1..8");
+    if (!dgw::fits_index32_2d(q->order, m.n_elems))
+        return dgw::set_error(DGW_ETOOBIG, "2D field arrays are limited to 2^32 values (32-bit partner-trace indices)");
     if (!(q->t_final > 0) || !std::isfinite(q->t_final)) return dgw::set_error(DGW_EINVAL, "t_final must be > 0");
     if (!(q->alpha >= 0.0 && q->alpha <= 1.0)) return dgw::set_error(DGW_EINVAL, "alpha must be in [0, 1]");
     if (q->prec != DGW_FP32) return dgw::set_error(DGW_EINVAL, "the server runs the FP32 path");

@@ -146,6 +146,10 @@ def test_error_paths_before_any_device_call():
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=4, device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=3, prec="split_bf16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, kernel=3, device=-1))
+    # a 2D field array of 2^32 values or more (N = 8: 3 * 45 * Kp >= 2^32 from
+    # Kp = 31814560 elements) is refused before the element array is read
+    big = inputs.Mesh(2, m.vx, m.vy, None, np.zeros((31_814_560, 3), np.int32))
+    _expect("DGW_ETOOBIG", lambda: dgw.Solver(big, 8, device=-1))
     # the FP64 field path is 2D only
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="fp64", device=-1))
     dgw.Solver(m, 3, prec="fp64", kernel=1, device=-1).close()
