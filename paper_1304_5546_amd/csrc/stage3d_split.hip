@@ -207,7 +207,10 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
             for (int mt = 0; mt < MT; ++mt)
                 acc[f][mt] = floatx4{cv[f][mt][0], cv[f][mt][1], cv[f][mt][2], cv[f][mt][3]};
         // own and partner traces of face-node slot t = 8 ks + q (node
-        // j = 32 ks + 8 g + q); two slots in flight ahead of the one in use
+        // j = 32 ks + 8 g + q), gathered RING - 1 slots ahead of their use.
+        // RING = 1 (no slot ahead) keeps the kernel within its 256
+        // registers; with a slot ahead registers spill and the order-4 stage
+        // runs 1.4 % slower
         auto gather = [&](int t, float (&m)[6], float (&pv)[6], int &wall) {
             const int j = 32 * (t >> 3) + 8 * g + (t & 7);
             const int jc = j < Nafp ? j : Nafp - 1;
@@ -225,7 +228,7 @@ __global__ void __launch_bounds__(256, 2) stage3d_split_kernel(StageArgs A) {
                 pv[f] = bload(rall, vp, f * Np * 256);
             }
         };
-        constexpr int NS = 8 * KL, RING = 2;
+        constexpr int NS = 8 * KL, RING = 1;
         float rm[RING][6], rp[RING][6];
         int rw[RING];
 #pragma unroll
