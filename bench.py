@@ -181,7 +181,7 @@ def main():
                          "traffic, for calibrating HBM byte counters in a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU halo exchange is design-only",
+        print(json.dumps({"error": "dgw runs on one GPU; the multi-GPU halo exchange is a design, not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.serve:
