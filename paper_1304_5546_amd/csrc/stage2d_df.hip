@@ -40,6 +40,7 @@ namespace dgw {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -118,7 +119,10 @@ struct TriD {
     static constexpr int LDS_MAX = 160 * 1024;
     static constexpr int WMAX = (sizeof(R) == 8 || N >= 7 || P == 2) ? 12 : 16;
     static constexpr int FIXED = (AV + AL) * (int)sizeof(R) + NT * 4;
-    static constexpr int WPB0 = (LDS_MAX - FIXED) / (FW * (int)sizeof(R));
+    // FP32 single-element lanes at order 5: the update goes through a second
+    // per-wave buffer and moves 16 bytes per lane
+    static constexpr bool TU = sizeof(R) == 4 && P == 1 && N == 5;
+    static constexpr int WPB0 = (LDS_MAX - FIXED) / ((TU ? 2 : 1) * FW * (int)sizeof(R));
     static constexpr int WPB = WPB0 >= WMAX ? WMAX : (WPB0 >= 12 ? 12 : (WPB0 >= 8 ? 8 : 4));
 };
 
@@ -213,6 +217,7 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
     __shared__ R sA[AV + AL];
     __shared__ int stab[NT];
     __shared__ R sF[WPB][T::FW];
+    __shared__ R sT[T::TU ? WPB : 1][T::TU ? T::FW : 1];  // right-hand side, for the update
 
     for (int i = threadIdx.x; i < AV + AL; i += 64 * WPB) sA[i] = X::frag(A)[i];
     for (int i = threadIdx.x; i < NT; i += 64 * WPB) stab[i] = A.itab[i];
@@ -369,14 +374,31 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
         constexpr int RG = X::RG, RJ = X::RJ;
         const __amdgpu_buffer_rsrc_t rr = rsrc(S.res + (size_t)tile * (3 * Np * 64), TB);
         const unsigned vout = (unsigned)(RG * g * 64 + col) * W;  // row RG g of column col
-        PV<R, P> rpre[RPF > 0 ? RPF : 1][MT][4];
+        PV<R, P> rpre[RPF > 0 && !T::TU ? RPF : 1][MT][4];
+        // TU: lane (r0t, qdt) = (lane / 4, lane % 4) owns columns 4 qdt ..
+        // 4 qdt + 3 of the unit's 16 in rows r0t + 16 i of the tile; the
+        // row is in the per-lane offset, the 16-row step in the (uniform)
+        // scalar offset.  The first RPT row groups are loaded here.
+        constexpr int NRT = 3 * Np, NIT = (NRT + 15) / 16, RPT = NIT < 2 ? NIT : 2;
+        const int r0t = lane >> 2, qdt = lane & 3;
+        const unsigned vq = (unsigned)(16 * (unit % UPT) + 4 * qdt) * 4 + (unsigned)r0t * ROW;
+        unsigned __int128 rpt[RPT];
+        if constexpr (T::TU) {
 #pragma unroll
-        for (int f = 0; f < RPF; ++f)
+            for (int i = 0; i < RPT; ++i)
+                rpt[i] = r0t + 16 * i < NRT
+                             ? __builtin_bit_cast(unsigned __int128,
+                                                  __builtin_amdgcn_raw_buffer_load_b128(rr, vq, (unsigned)(16 * i) * ROW, 0))
+                             : (unsigned __int128)0;
+        } else {
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int f = 0; f < RPF; ++f)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-                    rpre[f][mt][jj] = loadp<R, P>(rr, vout, (f * Np + 16 * mt + RJ * jj) * ROW);
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        rpre[f][mt][jj] = loadp<R, P>(rr, vout, (f * Np + 16 * mt + RJ * jj) * ROW);
+        }
         __builtin_amdgcn_sched_barrier(0);
 
         // ---- surface: flux at face node j = 4 ks + g, then LIFT
@@ -480,6 +502,44 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
         // 16 mt + RG g + RJ jj; rows >= Np are not stored.
         const __amdgpu_buffer_rsrc_t ro = rsrc(S.qout + (size_t)tile * (3 * Np * 64), TB);
         const R ca = X::a(A), cb = X::b(A), cdt = S.dt;
+        if constexpr (T::TU) {
+            // the right-hand side into the wave's second buffer (node-major,
+            // as the field copy), then per lane 4 consecutive columns of a
+            // row: one 16-byte load of res, one 16-byte store each of res
+            // and q_out
+            R *Tb = sT[w];
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int n = 16 * mt + RG * g + RJ * jj;
+                        if (n < Np) Tb[(f * Np + n) * FS + c] = acc[0][f][mt][jj];
+                    }
+#pragma unroll
+            for (int i = 0; i < NIT; ++i) {
+                const int r = r0t + 16 * i;
+                if (r < NRT) {
+                    // through a 128-bit integer: extracting the elements of
+                    // the vector result directly gets the load narrowed to
+                    // one dword by this compiler
+                    const unsigned __int128 ru =
+                        i < RPT ? rpt[i < RPT ? i : 0]
+                                : __builtin_bit_cast(unsigned __int128, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                            rr, vq, (unsigned)(16 * i) * ROW, 0));
+                    u32x4 rn, qn;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const R rk = ca * __builtin_bit_cast(R, (unsigned)(ru >> (32 * k))) + cdt * Tb[r * FS + 4 * qdt + k];
+                        rn[k] = __builtin_bit_cast(unsigned, rk);
+                        qn[k] = __builtin_bit_cast(unsigned, F[r * FS + 4 * qdt + k] + cb * rk);
+                    }
+                    __builtin_amdgcn_raw_buffer_store_b128(rn, rr, vq, (unsigned)(16 * i) * ROW, 0);
+                    __builtin_amdgcn_raw_buffer_store_b128(qn, ro, vq, (unsigned)(16 * i) * ROW, 0);
+                }
+            }
+        } else
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             PV<R, P> rv[MT][4], qv[MT][4];
@@ -488,7 +548,7 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const unsigned so = (f * Np + 16 * mt + RJ * jj) * ROW;
-                    rv[mt][jj] = f < RPF ? rpre[f < RPF ? f : 0][mt][jj] : loadp<R, P>(rr, vout, so);
+                    rv[mt][jj] = f < RPF && !T::TU ? rpre[f < RPF ? f : 0][mt][jj] : loadp<R, P>(rr, vout, so);
                     const int n = 16 * mt + RG * g + RJ * jj;
 #pragma unroll
                     for (int p = 0; p < P; ++p) qv[mt][jj].v[p] = n < Np ? F[(f * Np + n) * FS + P * c + p] : R(0);
