@@ -21,9 +21,14 @@ Every function is pinned in ``tests/test_oracle_*.py`` against closed forms,
 invariants and brute force: polynomial exactness of differentiation, the
 divergence theorem per element, closed-form PEC cavity modes, h-convergence of
 order N+1, energy decay under the upwind flux (conservation under the central
-flux), the stability polynomial of the RK scheme and a brute-force weak-form
-assembly.  Parity unpinned: none (the node-set parameter alpha_opt and the CFL
-constant are shared *inputs*, not method arithmetic).
+flux), the stability polynomial of the RK scheme, the strong-form operator
+against a weak form of eq. dg-weak assembled independently by quadrature
+(``tests/test_oracle_weak_form.py``), and the energy and relative-L2
+diagnostics against exact integrals of polynomial and piecewise-constant
+fields (``tests/test_oracle_norms.py``).  Planted mistakes (a dropped 1/2,
+a flipped sign, swapped material weights, a missing square root or
+Jacobian) fail those pins.  Parity unpinned: none (the node-set parameter
+alpha_opt and the CFL constant are shared *inputs*, not method arithmetic).
 """
 
 from .element import RefElement2D, RefElement3D, lgl_nodes  # noqa: F401
