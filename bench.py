@@ -2,14 +2,18 @@
 
 A "step" is one full five-stage LSRK4 step of the whole hot path (volume
 differentiation, face gather + upwind flux, LIFT, RK update, fused in one
-kernel per stage) over the 2D TM PEC cavity: 256x256 grid -> 131072
-randomly permuted, jittered triangles, order N=5 (Np=21), mode (2,3), CFL
-time step.  Inputs are resident in HBM before the timed region.
+kernel per stage).  Default workload: the 2D TM PEC cavity on a 512x512 grid
+-> 524288 jittered triangles, order N=7 (Np=36), mode (2,3), CFL time step,
+in FP32 (`value`), with the split-BF16 and split-FP16 forms timed beside it
+and every variant's relative L2 error against the closed-form mode at t = 1.
+Inputs are resident in HBM before the timed region.  A short serving leg
+(continuous batching of a seeded request mix) adds p50/p99 latency.
 
-    python bench.py [--steps K] [--warmup W] [--config c2|c3|c1|c5] [--prec P] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--config c3|c2|c1|c5] [--prec P]
+                    [--variants LIST] [--serve-short N] [--no-cpu]
 
-Prints one JSON line (metric, value, roofline, cpu_baseline, accuracy, and
-per precision variant the throughput and the relative L2 error at t = 1).
+Prints one JSON line (metric, value, roofline, cpu_baseline, accuracy, per
+precision variant the throughput and the L2 error at t = 1, serving).
 """
 
 from __future__ import annotations
@@ -113,20 +117,23 @@ def serve_run(n_requests: int, seed: int = 4, mode: str = "burst", rate: float =
         t0 = time.perf_counter()
         dof = 0.0
         lat = []
+        device_s = 0.0
         for r, m in zip(reqs, meshes):
             a = time.perf_counter()
             with dgw.Solver(m, r.order) as s:
                 s.set_cavity_mode(*r.mode)
                 n = s.advance(r.t_final)
+                device_s += s.info()["solve_ms"] * 1e-3
                 s.energy()
             dof += 3.0 * m.K * np_of[r.order] * n
             lat.append(time.perf_counter() - a)
-            if len(lat) % 32 == 0:
+            if len(lat) % 16 == 0:
                 print(f"[serve] sequential: {len(lat)}/{n_requests} done", file=sys.stderr, flush=True)
         span = time.perf_counter() - t0
         return {"mode": "sequential plain FP32 solver", "requests": n_requests, "makespan_s": span,
-                "dof_updates_per_s": dof / span, "p50_solve_s": float(np.percentile(lat, 50)),
-                "p99_solve_s": float(np.percentile(lat, 99))}
+                "dof_updates_per_s": dof / span, "device_s": device_s,
+                "device_dof_updates_per_s": dof / device_s,
+                "p50_solve_s": float(np.percentile(lat, 50)), "p99_solve_s": float(np.percentile(lat, 99))}
     arrivals = np.zeros(n_requests) if mode == "burst" else inputs.poisson_arrivals(n_requests, rate, seed + 1000)
     results = {}
     with dgw.Server(max_chunk_steps=max_chunk_steps) as srv:
@@ -145,7 +152,7 @@ def serve_run(n_requests: int, seed: int = 4, mode: str = "burst", rate: float =
         th.join()
         for i, t in enumerate(tickets):
             results[i] = srv.wait(t)[0]
-            if (i + 1) % 32 == 0:
+            if (i + 1) % 16 == 0:
                 print(f"[serve] {mode}: {i + 1}/{n_requests} collected", file=sys.stderr, flush=True)
         span = time.perf_counter() - t0
         st = srv.stats()
@@ -155,16 +162,31 @@ def serve_run(n_requests: int, seed: int = 4, mode: str = "burst", rate: float =
     return {"mode": f"server, {mode} arrivals" + (f" at {rate:.3g} req/s" if mode != "burst" else ""),
             "requests": n_requests, "completed_ok": ok, "makespan_s": span,
             "dof_updates_per_s": st["dof_updates"] / span,
+            "device_dof_updates_per_s": st["dof_updates"] / st["busy_s"],
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "p50_queue_s": float(np.percentile(queue, 50)), "busy_s": st["busy_s"]}
+
+
+def serving_leg(n: int):
+    """Short serving leg for the default line: the first n requests of the
+    seeded mix arriving at once (capacity), then the same requests with
+    Poisson arrivals at 0.8 x that capacity (p50/p99 latency), then one at a
+    time through the plain FP32 solver (device time of the same work)."""
+    burst = serve_run(n)
+    cap = burst["requests"] / burst["makespan_s"]
+    pois = serve_run(n, mode="poisson", rate=0.8 * cap)
+    seq = serve_run(n, sequential=True)
+    return {"poisson": pois, "burst": burst, "sequential_fp32": seq,
+            "capacity_vs_sequential": burst["dof_updates_per_s"] / seq["dof_updates_per_s"],
+            "device_time_vs_sequential": burst["device_dof_updates_per_s"] / seq["device_dof_updates_per_s"]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel", type=int, default=0,
                     help="2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-operand MFMA, 3 derivative-first MFMA")
@@ -172,41 +194,44 @@ def main():
                     help="arithmetic of the timed path (value and roofline)")
     ap.add_argument("--autotune", action="store_true",
                     help="time every kernel variant and launch shape first (dgw_autotune) and time the fastest")
-    ap.add_argument("--serve", action="store_true", help="run the serving configuration instead")
-    ap.add_argument("--serve-n", type=int, default=256, help="requests in the serving run")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip timing the other precision variants and their t=1 accuracy runs")
+    ap.add_argument("--serve", action="store_true", help="run the full serving configuration instead")
+    ap.add_argument("--serve-n", type=int, default=256, help="requests in the full serving run")
+    ap.add_argument("--serve-short", type=int, default=24,
+                    help="requests in the short serving leg of the default line (0: none)")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated precision variants timed beside --prec, each with its L2 error at "
+                         "t = 1 (default: fp32,split_bf16,split_fp16 in 2D, fp32,split_bf16 in 3D; 'none')")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB (a kernel of known "
                          "traffic, for calibrating HBM byte counters in a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "dgw runs on one GPU; the multi-GPU halo exchange is a design, not built",
+        print(json.dumps({"error": "this library runs on one GPU; running the path across several GPUs "
+                                   "(a halo exchange of face traces) is a design, not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.serve:
-        # the serving configuration: burst (capacity: `value`), then Poisson
-        # arrivals at 0.8 x that capacity (p50/p99 latency), then the same
-        # requests one at a time through the plain FP32 solver
-        burst = serve_run(args.serve_n)
-        cap = burst["requests"] / burst["makespan_s"]
-        pois = serve_run(args.serve_n, mode="poisson", rate=0.8 * cap)
-        seq = serve_run(args.serve_n, sequential=True)
-        out = {"metric": METRIC, "value": burst["dof_updates_per_s"], "unit": "DOF-updates/s", "n_gpus": 1,
-               "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        # the full serving configuration: burst (capacity: `value`), then
+        # Poisson arrivals at 0.8 x that capacity (p50/p99 latency), then the
+        # same requests one at a time through the plain FP32 solver
+        sv = serving_leg(args.serve_n)
+        out = {"metric": METRIC, "value": sv["burst"]["dof_updates_per_s"], "unit": "DOF-updates/s",
+               "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                "config": {"workload": f"serving: {args.serve_n} 2D TM cavity requests, s ~ U{{16..256}}, "
                                       "N in {3,5,7}, eps in {1, 2.25} by random disk, t_final ~ U[0.5, 2]",
                           "seed": 4},
-               "p50_latency_s": pois["p50_latency_s"], "p99_latency_s": pois["p99_latency_s"],
-               "serving": {"poisson": pois, "burst": burst, "sequential_fp32": seq,
-                           "capacity_vs_sequential": burst["dof_updates_per_s"] / seq["dof_updates_per_s"]}}
+               "p50_latency_s": sv["poisson"]["p50_latency_s"], "p99_latency_s": sv["poisson"]["p99_latency_s"],
+               "serving": sv}
         print(json.dumps(out))
         return
 
     import torch
 
     from paper_1304_5546_amd import dgw, inputs
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     s_grid, seed, permute, N, mode, desc = CONFIGS[args.config]
     dim = 3 if len(mode) == 3 else 2
@@ -219,7 +244,8 @@ def main():
 
     def timed(prec):
         """Warm up, then time exactly args.steps steps on the solver's stream
-        with HIP events; the fields start from the device-initialised mode."""
+        with HIP events recorded on that stream; the fields start from the
+        device-initialised mode."""
         solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec)
         dt = solver.cfl_dt()
         solver.set_cavity_mode(*mode)
@@ -235,14 +261,18 @@ def main():
         ms = ev0.elapsed_time(ev1)
         t_reached = (args.warmup + args.steps) * dt
         err = solver.cavity_error(*mode3, t_reached)
+        log(f"{prec}: {args.steps} steps in {ms:.2f} ms ({ms / (5 * args.steps) * 1e3:.1f} us per stage)")
         return solver, dt, ms, t_reached, err
 
     def err_at_t1(prec):
         with dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec) as s1:
             s1.set_cavity_mode(*mode)
             n = s1.advance(1.0)
-            return s1.cavity_error(*mode3, 1.0), n
+            e = s1.cavity_error(*mode3, 1.0)
+        log(f"{prec}: t = 1 in {n} steps, rel L2 vs closed form {e:.3e}")
+        return e, n
 
+    log(f"{args.config}: K = {mesh.K}, N = {N}")
     solver, dt, ms, t_reached, err = timed(args.prec)
     bytes_per_launch, flops_per_launch = solver.stage_cost()
     dofs = solver.n_fields * solver.K * solver.Np
@@ -286,18 +316,23 @@ def main():
     if solver.tune:
         out["autotune"] = solver.tune
     solver.close()
-    if not args.no_variants:
+    if args.variants is None:
+        vlist = ["fp32", "split_bf16", "split_fp16"] if dim == 2 else ["fp32", "split_bf16"]
+    else:
+        vlist = [] if args.variants == "none" else [v for v in args.variants.split(",") if v]
+    if vlist:
         # the same timed run for every precision variant, each with its
         # relative L2 error against the closed-form mode at t = 1
         var = {}
-        for prec in ("fp32", "split_bf16", "split_fp16", "fp64") if dim == 2 else ("fp32", "split_bf16"):
+        for prec in vlist:
             if prec == args.prec:
-                v_ms, v_err = ms, err
+                v_ms = ms
             else:
-                sv, _, v_ms, _, v_err = timed(prec)
+                sv, _, v_ms, _, _ = timed(prec)
                 sv.close()
             e1, n1 = err_at_t1(prec)
             var[prec] = {"value": dofs * args.steps / (v_ms * 1e-3), "ms_per_step": v_ms / args.steps,
+                         "us_per_stage": v_ms * 1e3 / (5 * args.steps),
                          "rel_l2_vs_closed_form_t1": e1, "steps_to_t1": n1}
         out["variants"] = var
     if args.copy_calib_mib > 0:
@@ -308,7 +343,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": n * 4, "bytes_written": n * 4}
+    if args.serve_short > 0:
+        log(f"serving leg: {args.serve_short} requests")
+        sv = serving_leg(args.serve_short)
+        out["p50_latency_s"] = sv["poisson"]["p50_latency_s"]
+        out["p99_latency_s"] = sv["poisson"]["p99_latency_s"]
+        out["serving"] = sv
     if not args.no_cpu and dim == 2:
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, N, mode)
     print(json.dumps(out))
 

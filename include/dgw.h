@@ -146,7 +146,15 @@ typedef struct {
 } dgw_info;
 
 /* Set up the discretisation of order `order` on `mesh` (host FP64), upload
- * operators and geometry, allocate the fields (zero).  Errors: EINVAL,
+ * operators and geometry, allocate the fields (zero).  The inputs are those of
+ * the section "A Precise Mathematical Problem Statement": the domain meshed by
+ * straight-sided simplices, the material eps, mu per element (eq.
+ * tm-maxwells), the PEC wall on every face without a neighbour; the order N
+ * fixes the local polynomial space of "Construction of the Method", and the
+ * operators Dr, Ds(, Dt), M, LIFT and the affine factors are built as in
+ * "Implementation Aspects" (eqs. dg-diff-local-to-global, dg-lift).  The
+ * caller's arrays are read during the call only; the handle is library-owned
+ * until dgw_destroy.  Errors: EINVAL,
  * EMESH, EORDER, ENOMEM, EDEVICE; ETOOBIG for 2^26 elements or more, for a
  * 2D field array of 2^32 values or more (n_fields * Np * K rounded up to 64
  * elements; partner traces are addressed by 32-bit element indices) and for
@@ -162,30 +170,49 @@ int dgw_node_coords(const dgw_solver *s, double *x, double *y, double *z);
 int dgw_cfl_dt(const dgw_solver *s, double *dt);
 
 /* Fields in/out, FP64 host arrays [n_fields][K][Np] (converted to the device
- * precision).  set_fields zeroes the RK residual and the time. */
+ * precision).  set_fields gives the initial value at t = 0 of the problem
+ * statement ("A Precise Mathematical Problem Statement") as nodal values;
+ * get_fields returns the fields at the time reached (t_final after
+ * dgw_advance).  set_fields zeroes the RK residual and the time.  Both copy
+ * through host memory synchronously; EINVAL for NULL, ENODEVICE for a
+ * host-only handle. */
 int dgw_set_fields(dgw_solver *s, const double *q);
 int dgw_get_fields(dgw_solver *s, double *q);
-/* Initialise on the device, in FP64, the closed-form PEC cavity mode at t=0:
+/* Initial value at t = 0 (problem statement) computed on the device in FP64:
+ * the closed-form PEC cavity mode of the 2D TM system (eq. tm-maxwells) or of
+ * the 3D system, sampled at the nodes:
  * 2D Ez = sin(m pi x) sin(n pi y), H = 0 (mode = {m, n, -});
  * 3D E = (n cos(m pi x) sin(n pi y) sin(l pi z), -m sin cos sin, 0), H = 0. */
 int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]);
 
-/* Take `nsteps` LSRK4 steps of size dt (dt <= 0: the CFL step).  Launches
- * five fused stage kernels per step on the solver's stream, no host sync
- * inside the loop; returns after the stream has drained. */
+/* Time integration by the explicit Runge-Kutta method of "Implementation
+ * Aspects" (read as the five-stage fourth-order 2N-storage scheme of
+ * Carpenter and Kennedy): take `nsteps` steps of size dt (dt <= 0: the CFL
+ * step), each stage res <- a_s res + dt L(q), q <- q + b_s res with L the
+ * operator of eq. dg-strong-explicit, fused into one kernel launch per stage
+ * on the solver's stream, no host sync inside the loop; returns after the
+ * stream has drained.  EDEVICE on a launch failure. */
 int dgw_advance_steps(dgw_solver *s, int64_t nsteps, double dt);
 /* Advance to t_final: with dt <= 0 the step is the CFL step shortened to
  * t_final / ceil(t_final / dt_cfl). */
 int dgw_advance(dgw_solver *s, double t_final, double dt, int64_t *steps_taken);
 
-/* One evaluation of the semi-discrete right-hand side L(q) by the same fused
- * stage kernel (RK coefficients a = 0, dt = 1, b = 0): q and rhs are FP64 host
- * arrays [n_fields][K][Np].  Leaves the solver's fields and residual
- * overwritten with q and L(q). */
+/* One evaluation of the semi-discrete right-hand side L(q) of eq.
+ * dg-strong-explicit: local differentiation with the chain rule (eq.
+ * dg-diff-local-to-global), the face jumps and upwind flux of eq.
+ * max2d-numflux (factor 1/2) with the PEC mirror state, and LIFT (eq.
+ * dg-lift) -- the operation of the CPU right-hand side and of the GPU volume
+ * and surface kernels of "A Minimal Implementation" -- evaluated by the same
+ * fused stage kernel (RK coefficients a = 0, dt = 1, b = 0).  q and rhs are
+ * caller-owned FP64 host arrays [n_fields][K][Np].  Leaves the solver's
+ * fields and residual overwritten with q and L(q).  EINVAL for NULL. */
 int dgw_rhs(dgw_solver *s, const double *q, double *rhs);
 
 /* FP64 device reduction of the discrete energy
- * 0.5 * sum_k J_k sum_f w_f q_f^T M q_f (w = mu for H, eps for E). */
+ * 0.5 * sum_k J_k sum_f w_f q_f^T M q_f (w = mu for H, eps for E): the
+ * M-norm (mass matrix of "Implementation Aspects", |A_k| M on element k) that
+ * the upwind flux of eq. max2d-numflux keeps non-increasing.  ENONFINITE
+ * when the result is not finite. */
 int dgw_energy(dgw_solver *s, double *energy);
 /* FP64 device reduction of the relative L2 error (mass-matrix norm, unit field
  * weights) of the current fields against the closed-form cavity mode at time

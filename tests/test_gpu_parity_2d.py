@@ -169,9 +169,12 @@ def test_c2_full_size_one_step_parity():
     q = q0.copy()
     res = np.zeros_like(q)
     op.lsrk4_step(q, res, dt)
-    err = rel(sol.get_fields(), q)
-    print(f"C2 one step: {err:.2e}")
+    got = sol.get_fields()
+    err = rel(got, q)
+    per_el = np.abs(got - q).max(axis=(0, 2)) / np.abs(q).max()
+    print(f"C2 one step: rel L2 {err:.2e}, worst element {int(per_el.argmax())} max-abs {per_el.max():.2e}")
     assert err < 1e-6
+    assert per_el.max() < 1e-5
 
 
 def test_c2_full_length_vs_closed_form():
