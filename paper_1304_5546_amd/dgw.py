@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdgw.so")
+# DGW_LIB selects another build of the same library (the host-sanitizer
+# build of the CPU tests); default: the in-tree libdgw.so
+LIB_PATH = os.environ.get("DGW_LIB") or os.path.join(_HERE, "libdgw.so")
 
 DGW_FP32, DGW_SPLIT_BF16, DGW_SPLIT_FP16, DGW_FP64 = 0, 1, 2, 3
 PRECISIONS = {"fp32": DGW_FP32, "split_bf16": DGW_SPLIT_BF16, "split_fp16": DGW_SPLIT_FP16, "fp64": DGW_FP64}
