@@ -214,6 +214,21 @@ int dgw_rhs(dgw_solver *s, const double *q, double *rhs);
  * the upwind flux of eq. max2d-numflux keeps non-increasing.  ENONFINITE
  * when the result is not finite. */
 int dgw_energy(dgw_solver *s, double *energy);
+/* Allocation-free form of dgw_energy, for callers that cannot allocate or
+ * synchronise (code under HIP graph capture, tight serving loops): the same
+ * FP64 reduction, bitwise the same value, written asynchronously on `stream`
+ * (a hipStream_t; NULL = the solver's stream) to energy_dev, a caller-owned
+ * device pointer to one double on the solver's device.  Calls no hipMalloc,
+ * hipFree, host synchronisation or allocating library routine: the per-block
+ * partial sums live in a static device array of the library (1024 doubles
+ * per device, set up by dgw_create; the reduction uses 512 of them and
+ * overwrites each one, so nothing needs clearing), shared by every call on
+ * that device: calls that overlap in time on one device race and must be
+ * ordered by the caller (one stream, or events).  No finiteness check (the
+ * value is not read back): the caller tests it.  Errors: EINVAL (NULL
+ * output), ENODEVICE, EDEVICE; ETOOBIG if the reduction needed more partials
+ * than the static array holds. */
+int dgw_energy_noalloc(dgw_solver *s, double *energy_dev, void *stream);
 /* FP64 device reduction of the relative L2 error (mass-matrix norm, unit field
  * weights) of the current fields against the closed-form cavity mode at time
  * t (2D: uniform eps, mu of element 0; 3D: eps = mu = 1). */

@@ -58,6 +58,15 @@ __global__ void __launch_bounds__(kRedThreads) energy_kernel(ReduceArgs a) {
     if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
 }
 
+// Sum of the n per-block partials in index order (the order of the host sum
+// of dgw_energy), scaled: one thread, so the result is bitwise that sum.
+__global__ void sum_partials_kernel(const double *partial, int n, double scale, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    *out = scale * s;
+}
+
 __device__ void cavity_exact(const CavityArgs &a, double x, double y, double z, double *out) {
     const double pi = M_PI;
     if (a.dim == 2) {
@@ -182,6 +191,12 @@ hipError_t launch_energy(const ReduceArgs &a, int nblocks, hipStream_t s) {
         hipLaunchKernelGGL(energy_kernel<true>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
     else
         hipLaunchKernelGGL(energy_kernel<false>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *partial, int n, double scale, double *out, hipStream_t s) {
+    if (!partial || !out || n < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partial, n, scale, out);
     return hipGetLastError();
 }
 

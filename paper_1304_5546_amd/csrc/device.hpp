@@ -150,6 +150,9 @@ struct ReduceArgs {
     double *partial;
 };
 hipError_t launch_energy(const ReduceArgs &a, int nblocks, hipStream_t stream);
+// *out = scale * (partial[0] + partial[1] + ... + partial[n-1]), summed in
+// index order by one device thread
+hipError_t launch_sum_partials(const double *partial, int n, double scale, double *out, hipStream_t stream);
 
 // Relative L2 vs the closed-form cavity mode at time t: partial[2*b] is the
 // error mass norm squared, partial[2*b+1] the reference's.

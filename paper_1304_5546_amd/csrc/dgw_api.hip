@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -40,6 +41,42 @@ using dgw::kRkA;
 using dgw::kRkB;
 
 constexpr int kRedBlocks = 512;
+
+}  // namespace
+
+// Reduction scratch of dgw_energy_noalloc: the per-block partial sums of the
+// energy kernel.  A file-scope device array, so that the call allocates
+// nothing; every device the library runs on holds its own copy until the
+// process ends.  In host code its name is only a stand-in: the device
+// address of each device's copy is looked up once per device at solver
+// set-up (with that device current) and kept in g_scratch_ptr.
+constexpr int kNoAllocPartials = 1024;  // doubles
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch copy; the device must be current.
+int init_scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(DGW_EINVAL, "device ordinal out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return DGW_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(DGW_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double *)p;
+    return DGW_OK;
+}
+
+double *scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -143,6 +180,7 @@ int setup_device(dgw_solver *s) {
     const auto &R = s->ref;
     DGW_HIP(hipSetDevice(s->opts.device));
     s->on_device = true;
+    if (int rc0 = init_scratch_ptr(s->opts.device)) return rc0;
     if (s->opts.hip_stream) {
         s->stream = (hipStream_t)s->opts.hip_stream;
     } else {
@@ -737,6 +775,33 @@ int dgw_energy(dgw_solver *s, double *energy) {
     for (double v : h) e += v;
     *energy = 0.5 * e;
     if (!std::isfinite(*energy)) return fail(DGW_ENONFINITE, "energy is not finite");
+    return DGW_OK;
+}
+
+int dgw_energy_noalloc(dgw_solver *s, double *energy_dev, void *stream) {
+    int rc = need_device(s);
+    if (rc) return rc;
+    if (!energy_dev) return fail(DGW_EINVAL, "NULL output");
+    static_assert(kRedBlocks <= kNoAllocPartials, "energy partials exceed the static scratch");
+    if (kRedBlocks > kNoAllocPartials)
+        return fail(DGW_ETOOBIG, "energy reduction needs more partials than the static scratch holds");
+    double *ptr = scratch_ptr(s->opts.device);
+    if (!ptr) return fail(DGW_EDEVICE, "scratch address of this device not set up");
+    DGW_HIP(hipSetDevice(s->opts.device));
+    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    dgw::ReduceArgs a{};
+    a.q = s->q[s->cur];
+    a.q64 = s->q64[s->cur];
+    a.J = s->J_d;
+    a.Mref = s->M_d;
+    a.w = s->w_d;
+    a.Kp = (int)s->Kp;
+    a.K = (int)s->K;
+    a.Np = s->Np;
+    a.nf = s->nf;
+    a.partial = ptr;  // every block writes its slot: nothing to clear
+    DGW_HIP(dgw::launch_energy(a, kRedBlocks, st));
+    DGW_HIP(dgw::launch_sum_partials(ptr, kRedBlocks, 0.5, energy_dev, st));
     return DGW_OK;
 }
 

@@ -120,6 +120,7 @@ def lib() -> C.CDLL:
             "dgw_advance": (C.c_int, [P, D, D, P]),
             "dgw_rhs": (C.c_int, [P, P, P]),
             "dgw_energy": (C.c_int, [P, P]),
+            "dgw_energy_noalloc": (C.c_int, [P, P, P]),
             "dgw_cavity_error": (C.c_int, [P, P, D, P]),
             "dgw_last_info": (C.c_int, [P, P]),
             "dgw_set_fields_dev": (C.c_int, [P, P, P]),
@@ -277,6 +278,12 @@ class Solver:
         e = C.c_double()
         _check(lib().dgw_energy(self._h, C.byref(e)), "dgw_energy")
         return e.value
+
+    def energy_noalloc(self, out_tensor, stream=None):
+        """dgw_energy_noalloc: the energy written asynchronously to a one-element
+        FP64 device tensor on `stream` (None: the solver's stream)."""
+        _check(lib().dgw_energy_noalloc(self._h, C.c_void_p(out_tensor.data_ptr()), self._stream_ptr(stream)),
+               "dgw_energy_noalloc")
 
     def cavity_error(self, m: int, n: int, l: int, t: float) -> float:
         mode = (C.c_int32 * 3)(m, n, l)
