@@ -282,7 +282,7 @@ def main():
     pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2, "fp64": 3}[args.prec]
     variant = solver.info()["kernel"]
     if dim == 3:
-        kname = f"stage3d_split_kernel<{N}>" if pcode else f"stage3d_kernel<{N}>"
+        kname = f"stage3d_kernel<{N}, {'true' if pcode else 'false'}>"
     elif pcode == 3:
         kname = f"stage2d_kernel<double, {N}, false>" if variant == 1 else f"stage2d_df_kernel<double, {N}, false, 1>"
     elif pcode:

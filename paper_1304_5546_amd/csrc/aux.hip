@@ -45,9 +45,9 @@ __global__ void __launch_bounds__(kRedThreads) energy_kernel(ReduceArgs a) {
         for (int f = 0; f < a.nf; ++f) {
             double qf = 0.0;
             for (int i = 0; i < a.Np; ++i) {
-                const double qi = qval<D64>(a, tix(e, f * a.Np + i, a.nf * a.Np));
+                const double qi = qval<D64>(a, fidx(e, f, i, a.nf, a.Np, a.npp));
                 double mq = 0.0;
-                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * qval<D64>(a, tix(e, f * a.Np + j, a.nf * a.Np));
+                for (int j = 0; j < a.Np; ++j) mq += a.Mref[i * a.Np + j] * qval<D64>(a, fidx(e, f, j, a.nf, a.Np, a.npp));
                 qf += qi * mq;
             }
             ek += (a.w ? a.w[tix(e, f, a.nf)] : 1.0) * qf;
@@ -111,7 +111,7 @@ __global__ void cavity_init_kernel(CavityArgs a) {
             cavity_exact(a, a.x[p], a.y[p], a.dim == 3 ? a.z[p] : 0.0, out);
         }
         for (int f = 0; f < nf; ++f) {
-            const size_t p = tix(e, f * a.Np + i, nf * a.Np);
+            const size_t p = fidx(e, f, i, nf, a.Np, a.npp);
             if constexpr (D64)
                 a.q64[p] = out[f];
             else
@@ -134,14 +134,14 @@ __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a)
             const size_t pi = tix(e, i, a.Np);
             double exi[6], di[6], md[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
             cavity_exact(a, a.x[pi], a.y[pi], a.dim == 3 ? a.z[pi] : 0.0, exi);
-            for (int f = 0; f < nf; ++f) di[f] = qval<D64>(a, tix(e, f * a.Np + i, nf * a.Np)) - exi[f];
+            for (int f = 0; f < nf; ++f) di[f] = qval<D64>(a, fidx(e, f, i, nf, a.Np, a.npp)) - exi[f];
             for (int j = 0; j < a.Np; ++j) {
                 const size_t pj = tix(e, j, a.Np);
                 double exj[6];
                 cavity_exact(a, a.x[pj], a.y[pj], a.dim == 3 ? a.z[pj] : 0.0, exj);
                 const double Mij = a.Mref[i * a.Np + j];
                 for (int f = 0; f < nf; ++f) {
-                    md[f] += Mij * (qval<D64>(a, tix(e, f * a.Np + j, nf * a.Np)) - exj[f]);
+                    md[f] += Mij * (qval<D64>(a, fidx(e, f, j, nf, a.Np, a.npp)) - exj[f]);
                     mx[f] += Mij * exj[f];
                 }
             }
@@ -161,24 +161,36 @@ __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a)
     }
 }
 
-__global__ void to_internal_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf) {
-    const size_t total = (size_t)nf * Np * Kp;
+// every slot of the internal array is written (padding elements and pad
+// nodes with 0)
+__global__ void to_internal_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+                                   int npp) {
+    const size_t total = npp ? (size_t)Kp * nf * npp : (size_t)nf * Np * Kp;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        const int rows = nf * Np;
-        const int e = int((t / ((size_t)64 * rows)) * 64 + (t & 63));
-        const int row = int((t / 64) % rows);
-        const int n = row % Np, f = row / Np;
-        dst[t] = e < K ? src[((size_t)f * K + perm[e]) * Np + n] : 0.0f;
+        int e, n, f;
+        if (npp) {
+            n = int(t % npp);
+            f = int((t / npp) % nf);
+            e = int(t / ((size_t)npp * nf));
+        } else {
+            const int rows = nf * Np;
+            e = int((t / ((size_t)64 * rows)) * 64 + (t & 63));
+            const int row = int((t / 64) % rows);
+            n = row % Np;
+            f = row / Np;
+        }
+        dst[t] = (e < K && n < Np) ? src[((size_t)f * K + perm[e]) * Np + n] : 0.0f;
     }
 }
 
-__global__ void to_caller_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf) {
+__global__ void to_caller_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+                                 int npp) {
     const size_t total = (size_t)nf * Np * K;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
         const int e = int(t % K);
         const size_t fn = t / K;
         const int n = int(fn % Np), f = int(fn / Np);
-        dst[((size_t)f * K + perm[e]) * Np + n] = src[tix(e, f * Np + n, nf * Np)];
+        dst[((size_t)f * K + perm[e]) * Np + n] = src[fidx(e, f, n, nf, Np, npp)];
     }
 }
 
@@ -218,15 +230,15 @@ hipError_t launch_cavity_error(const CavityArgs &a, int nblocks, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_to_internal(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+hipError_t launch_to_internal(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf, int npp,
                               hipStream_t s) {
-    hipLaunchKernelGGL(to_internal_kernel, dim3(2048), dim3(256), 0, s, src, dst, perm, K, Kp, Np, nf);
+    hipLaunchKernelGGL(to_internal_kernel, dim3(2048), dim3(256), 0, s, src, dst, perm, K, Kp, Np, nf, npp);
     return hipGetLastError();
 }
 
-hipError_t launch_to_caller(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+hipError_t launch_to_caller(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf, int npp,
                             hipStream_t s) {
-    hipLaunchKernelGGL(to_caller_kernel, dim3(2048), dim3(256), 0, s, src, dst, perm, K, Kp, Np, nf);
+    hipLaunchKernelGGL(to_caller_kernel, dim3(2048), dim3(256), 0, s, src, dst, perm, K, Kp, Np, nf, npp);
     return hipGetLastError();
 }
 

@@ -34,6 +34,27 @@ __host__ __device__ inline size_t tix(int64_t e, int row, int rows) {
     return ((size_t)(e >> 6) * rows + row) * 64 + (size_t)(e & 63);
 }
 
+// Field arrays (q, res).  2D: the tiled layout, row f*Np + n of element e
+// at tix(e, f*Np + n, nf*Np).  3D: element-major, element e's fields one
+// after another, each padded to npp = Np rounded up to 4 nodes
+// ([e][f][npp], the pad nodes hold 0): one element's values form one
+// contiguous block, so the face traces of a partner element touch a few
+// cache lines instead of one line per node.  npp == 0 selects the 2D form.
+__host__ __device__ inline size_t fidx(int64_t e, int f, int n, int nf, int Np, int npp) {
+    return npp ? ((size_t)e * nf + f) * npp + n : tix(e, f * Np + n, nf * Np);
+}
+__host__ __device__ constexpr int npp3d(int Np) { return (Np + 3) / 4 * 4; }
+
+// Nodes owned by lane group g (g = 0..3, lanes 16 g .. 16 g + 15) in the 3D
+// kernels: slot i = 0..kv-1 (kv = npp / 4) holds node slot_node(kv, g, i).
+// Slots come in runs of four consecutive nodes (one 16-byte access per
+// lane), 16 nodes per run of the four lane groups; the remaining kv mod 4
+// slots hold nodes 16 (kv/4) + 4 r + g.  Over the four lane groups every
+// node 0..npp-1 appears once.
+__host__ __device__ constexpr int slot_node(int kv, int g, int i) {
+    return i < 4 * (kv / 4) ? 16 * (i / 4) + 4 * g + (i % 4) : 16 * (kv / 4) + 4 * (i - 4 * (kv / 4)) + g;
+}
+
 // The 2D fused-operand and split kernels address partner traces by 32-bit
 // element indices into the [tile][3 Np][64] field array: true when the array
 // of a 2D solve of order N on K elements stays below 2^32 values.
@@ -102,7 +123,8 @@ int blocks_per_cu_2d_batch(int N, bool material);
 // with out == nullptr returns the required length
 int opsfrag2d(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
 int face_node2d(int N, int f, int t);
-// fragment-ordered fused operator [Dr | Ds | Dt | LIFT] of the 3D kernel
+// operator fragments of the 3D FP32 kernel (packed [Dr; Ds; Dt], LIFT; see
+// stage3d.hip); with out == nullptr returns the number of floats
 int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, float *out);
 // resident work-groups per CU of the persistent 2D MFMA kernel
 int blocks_per_cu_2d_mfma(int N, bool material);
@@ -141,6 +163,7 @@ int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt,
 //   energy: J_k sum_f w_f q_f^T M q_f     (w from wvec: [n_fields][Kp] FP64 or NULL = 1)
 // into partial[nblocks].
 struct ReduceArgs {
+    int npp;              // field layout (fidx): 0 = 2D tiled, else the 3D padded node count
     const float *q;
     const double *q64;    // FP64 fields (FP64 solvers; q unused then)
     const double *J;      // [Kp]
@@ -157,6 +180,7 @@ hipError_t launch_sum_partials(const double *partial, int n, double scale, doubl
 // Relative L2 vs the closed-form cavity mode at time t: partial[2*b] is the
 // error mass norm squared, partial[2*b+1] the reference's.
 struct CavityArgs {
+    int npp;              // field layout (fidx): 0 = 2D tiled, else the 3D padded node count
     float *q;             // fields (written by init, read by error)
     double *q64;          // FP64 fields instead (FP64 solvers)
     const double *x, *y, *z;   // node coordinates [Np][Kp]
@@ -171,10 +195,10 @@ hipError_t launch_cavity_init(const CavityArgs &a, hipStream_t stream);
 hipError_t launch_cavity_error(const CavityArgs &a, int nblocks, hipStream_t stream);
 
 // Layout permutation between the caller's [nf][K][Np] FP32 and the internal
-// node-major [nf][Np][Kp]; perm[e] = caller element at internal e (e < K).
-hipError_t launch_to_internal(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+// field layout (fidx with npp); perm[e] = caller element at internal e (e < K).
+hipError_t launch_to_internal(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf, int npp,
                               hipStream_t stream);
-hipError_t launch_to_caller(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
+hipError_t launch_to_caller(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf, int npp,
                             hipStream_t stream);
 
 }  // namespace dgw

@@ -91,7 +91,8 @@ int64_t solver_footprint(int dim, int order, int64_t K, bool material, int prec)
     const int64_t G = dim == 2 ? (material ? 6 : 4) : 9, FG = dim == 2 ? (material ? 6 : 3) : 4;
     const int64_t Kp = (K + kTile - 1) / kTile * kTile;
     const int64_t wq = prec == DGW_FP64 ? 8 : 4;        // bytes per field value
-    int64_t b = 3 * nf * Np * Kp * wq;                   // q ping-pong and res
+    const int64_t npp = dim == 3 ? dgw::npp3d((int)Np) : Np;  // 3D: nodes padded to 4 per field
+    int64_t b = 3 * nf * npp * Kp * wq;                  // q ping-pong and res
     b += (G + Nf * FG) * Kp * 4 + Nf * Kp * 4;          // factors and face records
     if (prec != DGW_FP32) b += (G + Nf * FG) * Kp * 8;  // FP64 factors
     const int64_t MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nf * Nfp + 3) / 4;
@@ -189,7 +190,7 @@ int setup_device(dgw_solver *s) {
     }
     DGW_HIP(hipEventCreate(&s->ev0));
     DGW_HIP(hipEventCreate(&s->ev1));
-    const size_t nstate = (size_t)nf * Np * Kp;
+    const size_t nstate = s->state_size();
     int rc;
     if (s->fp64) {
         if ((rc = dalloc(&s->q64[0], nstate)) || (rc = dalloc(&s->q64[1], nstate)) || (rc = dalloc(&s->res64, nstate)))
@@ -417,12 +418,12 @@ template <typename T>
 int upload_fields_t(dgw_solver *s, const double *q, T *dst) {
     const int Np = s->Np, nf = s->nf;
     const int64_t K = s->K, Kp = s->Kp;
-    std::vector<T> h((size_t)nf * Np * Kp, T(0));
+    std::vector<T> h(s->state_size(), T(0));
     for (int f = 0; f < nf; ++f)
         for (int64_t e = 0; e < K; ++e) {
             const int64_t k = s->perm[e];
             const double *src = q + ((size_t)f * K + k) * Np;
-            for (int n = 0; n < Np; ++n) h[dgw::tix(e, f * Np + n, nf * Np)] = (T)src[n];
+            for (int n = 0; n < Np; ++n) h[dgw::fidx(e, f, n, nf, Np, s->npp)] = (T)src[n];
         }
     DGW_HIP(hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
     return DGW_OK;
@@ -434,7 +435,7 @@ int upload_fields(dgw_solver *s, const double *q) {
 
 // zero the RK residual (asynchronously on st)
 int clear_res(dgw_solver *s, hipStream_t st) {
-    const size_t n = (size_t)s->nf * s->Np * s->Kp;
+    const size_t n = s->state_size();
     if (s->fp64)
         DGW_HIP(hipMemsetAsync(s->res64, 0, n * sizeof(double), st));
     else
@@ -446,14 +447,14 @@ template <typename T>
 int download(dgw_solver *s, const T *src_d, double *out) {
     const int Np = s->Np, nf = s->nf;
     const int64_t K = s->K, Kp = s->Kp;
-    std::vector<T> h((size_t)nf * Np * Kp);
+    std::vector<T> h(s->state_size());
     DGW_HIP(hipStreamSynchronize(s->stream));
     DGW_HIP(hipMemcpy(h.data(), src_d, h.size() * sizeof(T), hipMemcpyDeviceToHost));
     for (int f = 0; f < nf; ++f)
         for (int64_t e = 0; e < K; ++e) {
             const int64_t k = s->perm[e];
             double *dst = out + ((size_t)f * K + k) * Np;
-            for (int n = 0; n < Np; ++n) dst[n] = h[dgw::tix(e, f * Np + n, nf * Np)];
+            for (int n = 0; n < Np; ++n) dst[n] = h[dgw::fidx(e, f, n, nf, Np, s->npp)];
         }
     return DGW_OK;
 }
@@ -590,7 +591,8 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     s->nf = s->dim == 2 ? 3 : 6;
     s->K = mesh->n_elems;
     s->Kp = (s->K + dgw::kTile - 1) / dgw::kTile * dgw::kTile;
-    if (s->dim == 3 && (int64_t)s->nf * s->Np * s->Kp * 4 >= (int64_t(1) << 31)) {
+    s->npp = s->dim == 3 ? dgw::npp3d(s->Np) : 0;
+    if (s->dim == 3 && (int64_t)s->state_size() * 4 >= (int64_t(1) << 31)) {
         delete s;
         return fail(DGW_ETOOBIG, "3D field arrays are limited to 2 GiB (partner traces use 32-bit byte offsets)");
     }
@@ -680,6 +682,7 @@ int dgw_set_cavity_mode(dgw_solver *s, const int32_t mode[3]) {
     if (!mode) return fail(DGW_EINVAL, "NULL mode");
     DGW_HIP(hipSetDevice(s->opts.device));
     dgw::CavityArgs a{};
+    a.npp = s->npp;
     a.q = s->q[s->cur];
     a.q64 = s->q64[s->cur];
     a.x = s->x_d;
@@ -757,6 +760,7 @@ int dgw_energy(dgw_solver *s, double *energy) {
     if (!energy) return fail(DGW_EINVAL, "NULL output");
     DGW_HIP(hipSetDevice(s->opts.device));
     dgw::ReduceArgs a{};
+    a.npp = s->npp;
     a.q = s->q[s->cur];
     a.q64 = s->q64[s->cur];
     a.J = s->J_d;
@@ -790,6 +794,7 @@ int dgw_energy_noalloc(dgw_solver *s, double *energy_dev, void *stream) {
     DGW_HIP(hipSetDevice(s->opts.device));
     hipStream_t st = stream ? (hipStream_t)stream : s->stream;
     dgw::ReduceArgs a{};
+    a.npp = s->npp;
     a.q = s->q[s->cur];
     a.q64 = s->q64[s->cur];
     a.J = s->J_d;
@@ -811,6 +816,7 @@ int dgw_cavity_error(dgw_solver *s, const int32_t mode[3], double t, double *rel
     if (!mode || !rel_l2) return fail(DGW_EINVAL, "NULL argument");
     DGW_HIP(hipSetDevice(s->opts.device));
     dgw::CavityArgs a{};
+    a.npp = s->npp;
     a.q = s->q[s->cur];
     a.q64 = s->q64[s->cur];
     a.x = s->x_d;
@@ -858,7 +864,8 @@ int dgw_set_fields_dev(dgw_solver *s, const float *q_dev, void *stream) {
     if (s->fp64) return fail(DGW_EINVAL, "FP32 device fields given to an FP64 solver");
     hipStream_t st = stream ? (hipStream_t)stream : s->stream;
     DGW_HIP(hipSetDevice(s->opts.device));
-    DGW_HIP(dgw::launch_to_internal(q_dev, s->q[s->cur], s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf, st));
+    DGW_HIP(dgw::launch_to_internal(q_dev, s->q[s->cur], s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf,
+                                    s->npp, st));
     if ((rc = clear_res(s, st))) return rc;
     s->t = 0.0;
     return DGW_OK;
@@ -871,7 +878,8 @@ int dgw_get_fields_dev(dgw_solver *s, float *q_dev, void *stream) {
     if (s->fp64) return fail(DGW_EINVAL, "FP32 device fields requested from an FP64 solver");
     hipStream_t st = stream ? (hipStream_t)stream : s->stream;
     DGW_HIP(hipSetDevice(s->opts.device));
-    DGW_HIP(dgw::launch_to_caller(s->q[s->cur], q_dev, s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf, st));
+    DGW_HIP(dgw::launch_to_caller(s->q[s->cur], q_dev, s->perm_d, (int)s->K, (int)s->Kp, s->Np, s->nf,
+                                    s->npp, st));
     return DGW_OK;
 }
 
@@ -912,7 +920,7 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     if ((int)cand.size() > DGW_TUNE_MAX) cand.resize(DGW_TUNE_MAX);
     // save the state (fields, residual, ping-pong index), try every
     // candidate on the solver's own buffers, restore the state bitwise
-    const size_t nstate = (size_t)s->nf * s->Np * s->Kp, bytes = nstate * (s->fp64 ? 8 : 4);
+    const size_t nstate = s->state_size(), bytes = nstate * (s->fp64 ? 8 : 4);
     void *cur_d = s->fp64 ? (void *)s->q64[s->cur] : (void *)s->q[s->cur];
     void *res_d = s->fp64 ? (void *)s->res64 : (void *)s->res;
     void *save = nullptr;

@@ -17,6 +17,9 @@ struct dgw_solver {
     dgw::Geometry g;
     int dim = 2, N = 1, Np = 0, Nfp = 0, Nfaces = 0, nf = 0;
     int64_t K = 0, Kp = 0;
+    int npp = 0;  // field layout (dgw::fidx): 0 = 2D tiled, 3D: padded nodes per field
+    // values in one field array (q, res)
+    size_t state_size() const { return npp ? (size_t)Kp * nf * npp : (size_t)nf * Np * Kp; }
     int G = 0, FG = 0;
     bool material = false;
     dgw_opts opts{};

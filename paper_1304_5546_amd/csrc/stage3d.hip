@@ -1,10 +1,12 @@
-// Fused LSRK stage for 3D Maxwell on tetrahedra (eps = mu = 1), FP32, with
-// the element-local contractions on the matrix cores (v_mfma_f32_16x16x4_f32).
+// Fused LSRK stage for 3D Maxwell on tetrahedra (eps = mu = 1), with the
+// element-local contractions on the matrix cores: FP32 products
+// (v_mfma_f32_16x16x4_f32) or split-BF16 products
+// (v_mfma_f32_16x16x32_bf16, Op b = Op_hi b_hi + Op_hi b_lo + Op_lo b_hi,
+// x_hi = bf16(x), x_lo = bf16(x - x_hi), FP32 accumulation).
 //
 // 3D analogue of eq. dg-strong-explicit (section "Adding Generality": the
 // kernels change only mildly).  Per element and stage:
-//   1. reference derivatives D_p u (p = r, s, t) of each of the six fields u
-//      (MFMA: [Dr; Ds; Dt] against the field's nodal values);
+//   1. reference derivatives D_p u (p = r, s, t) of each of the six fields u;
 //   2. chain rule and curl on those derivatives (eq. dg-diff-local-to-global,
 //      g_p = grad p constant per affine element):
 //        rhs_H = -curl E,  rhs_E = curl H,  d_x u = sum_p (p_x) D_p u, ...;
@@ -14,26 +16,49 @@
 //        flux_E = Fscale/2 (-n x [H] + alpha (n (n.[E]) - [E]) ),
 //      the partner trace through the face record and the orientation table,
 //      on the PEC wall the mirror state E+ = -E-, H+ = H-;
-//   4. rhs += LIFT flux (MFMA), then res <- a res + dt rhs,
-//      q_out <- q_in + b res.
+//   4. rhs += LIFT flux, then res <- a res + dt rhs, q_out <- q_in + b res.
+// The split form keeps the geometric factors, normals and Fscale in FP64:
+// the chain rule and the flux are evaluated in FP64 and rounded to FP32 once;
+// its derivative operand is u - u(node 0) (D_p annihilates constants, so the
+// split carries the variation of u across the element, not its mean).
 //
-// Work unit = one wave and 16 consecutive elements (one MFMA N-tile; lane
-// (g, c) = (lane / 16, lane % 16) works on element column c).  The operands
-// of the derivatives are read straight from HBM (buffer loads sharing one
-// address register per lane): the B fragment of K-step ks is rows 4 ks + g
-// of the field, a 64-byte piece of each of four 256-byte rows; the eight
-// waves of a work-group take the quarters of two 64-element tiles together.
-// As they arrive the values are also written to the wave's LDS copy of its
-// elements' fields, from which the face traces and the update read them (no
-// second trip to memory).  The LDS also holds the operator fragments and the
-// face-node tables.  Persistent grid with XCD-contiguous ranges of tiles.
+// Field layout: element-major, [element][field][node] with each field padded
+// to NPP = Np rounded up to 4 nodes.  A work unit is one wave and 16
+// elements (one MFMA N-tile, lane (g, c) = (lane / 16, lane % 16) works on
+// element c).  Lane group g owns the nodes slot_node(KV, g, i), i < KV:
+// runs of four consecutive nodes, so operands, residual and new fields move
+// as one 16-byte access per lane and run.  The output rows of every
+// contraction are permuted to the same ownership, so the accumulators of a
+// lane hold exactly the nodes it loads and stores:
+//   - the FP32 derivative operator is [Dr; Ds; Dt] packed by output slot:
+//     slot s = 4 mt + jj of lane group g holds D_(s mod 3) of node
+//     slot_node(KV, g, s / 3), so one lane finds the three reference
+//     derivatives of a node in its own registers (7 M-tiles at order 4
+//     instead of 3 x 3); its K rows follow the same ownership (row 4 ks + g
+//     is node slot_node(KV, g, ks));
+//   - the split derivative operator has the same rows, K rows in node order
+//     (lane group g holds K rows 32 ks + 8 g .. + 7: two 16-byte runs);
+//   - LIFT rows follow the ownership (slot 4 mt + jj = node slot i), its K
+//     rows are the face nodes in face order.
+// The wave copies its elements' fields into LDS as they arrive; face traces
+// and the update read them there.  A work-group (8 waves) takes a pair of
+// 64-element tiles: partner traces inside the pair come from the other
+// waves' LDS copies, the rest from memory (one contiguous element block per
+// partner).  Persistent grid with XCD-contiguous ranges of tile pairs.
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 
 namespace dgw {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -42,17 +67,36 @@ struct Tet {
     static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
     static constexpr int Nfp = (N + 1) * (N + 2) / 2;
     static constexpr int Nafp = 4 * Nfp;
-    static constexpr int MT = (Np + 15) / 16;   // M-tiles of the output nodes
-    static constexpr int KV = (Np + 3) / 4;     // K-steps of a derivative
-    static constexpr int KL = (Nafp + 3) / 4;   // K-steps of LIFT
-    static constexpr int AV = 3 * MT * KV * 64; // derivative fragments (floats)
-    static constexpr int AL = MT * KL * 64;     // LIFT fragments
-    static constexpr int NT = Nafp + 4 * 6 * Nfp;  // face-node tables
+    static constexpr int NPP = npp3d(Np);        // nodes per field in memory
+    static constexpr int KV = NPP / 4;           // nodes per lane group
+    static constexpr int NC = KV / 4;            // 16-byte runs per lane and field
+    static constexpr int NR = KV - 4 * NC;       // single nodes per lane and field
+    static constexpr int MTD = (3 * KV + 3) / 4; // M-tiles of the packed derivative operator
+    static constexpr int MTL = (KV + 3) / 4;     // M-tiles of LIFT
+    static constexpr int KL = (Nafp + 3) / 4;    // K-steps of LIFT, FP32
+    // split derivative: 16-bit K steps of 32 nodes; when at least one is full
+    // and at most 8 nodes remain, those are contracted in FP32 (KT K steps of
+    // 4) instead of a mostly empty 16-bit step
+    static constexpr int TAILN = NPP % 32;
+    static constexpr bool TAIL = NPP >= 32 && TAILN > 0 && TAILN <= 8;
+    static constexpr int KVS = TAIL ? NPP / 32 : (NPP + 31) / 32;  // 16-bit K steps of a derivative
+    static constexpr int KT = TAIL ? TAILN / 4 : 0;                 // FP32 K steps of its tail
+    static constexpr int KLS = (Nafp + 31) / 32; // K-steps of LIFT, split
+    static constexpr int RS = 6 * NPP;           // floats per element
+    static constexpr int ES = RS + 4;            // LDS stride of an element's copy
+    static constexpr int NT = Nafp + 4 * 6 * Nfp;
+    // operator fragments: FP32 floats (derivative, then LIFT); split uint4
+    // (8 BF16) hi parts (derivative, LIFT) then lo parts
+    static constexpr int AV = MTD * KV * 64, AL = MTL * KL * 64;
+    static constexpr int FV = MTD * KVS * 64, FL = MTL * KLS * 64;
+    static constexpr int FT = MTD * KT * 64;  // FP32 tail fragments (floats), after the lo parts
+    static_assert(16 * NC <= Np, "a 16-byte run holds no pad node");
 };
 
 // Buffer resource over `bytes` bytes at a wave-uniform base: loads through it
-// take one per-lane 32-bit offset plus a scalar offset (the row), so rows of
-// a tile share one address register; accesses past `bytes` read 0 / drop.
+// take one per-lane 32-bit offset plus a scalar offset, so the runs and
+// fields of an element share one address register per lane; accesses past
+// `bytes` read 0 / drop.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
@@ -62,38 +106,95 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
+// 16-byte load into four floats (through a 128-bit integer: extracting the
+// lanes of the vector result directly lets the compiler narrow the load)
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float *v) {
+    const unsigned __int128 u = __builtin_bit_cast(unsigned __int128, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = __builtin_bit_cast(float, (unsigned)(u >> (32 * k)));
+}
+__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, const float *v, unsigned voff, unsigned soff) {
+    u32x4 u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = __builtin_bit_cast(unsigned, v[k]);
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, soff, 0);
+}
+__device__ __forceinline__ floatx4 mfma3(bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 bl, floatx4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) {
+    bf16x8 v;
+    __builtin_memcpy(&v, &u, 16);
+    return v;
+}
+
+// Curl contributions of the derivatives (gx, gy, gz) of field f (0..5 =
+// Hx, Hy, Hz, Ex, Ey, Ez) to the right-hand sides: rhs_H = -curl E,
+// rhs_E = curl H.
+template <int F, typename V>
+__device__ __forceinline__ void curl_add(V gx, V gy, V gz, float &o0, float &o1, float &o2, float &o3, float &o4,
+                                         float &o5) {
+    if constexpr (F == 0) { o4 += (float)gz; o5 -= (float)gy; }  // Ey += dz Hx, Ez -= dy Hx
+    if constexpr (F == 1) { o3 -= (float)gz; o5 += (float)gx; }  // Ex -= dz Hy, Ez += dx Hy
+    if constexpr (F == 2) { o3 += (float)gy; o4 -= (float)gx; }  // Ex += dy Hz, Ey -= dx Hz
+    if constexpr (F == 3) { o1 -= (float)gz; o2 += (float)gy; }  // Hy -= dz Ex, Hz += dy Ex
+    if constexpr (F == 4) { o0 += (float)gz; o2 -= (float)gx; }  // Hx += dz Ey, Hz -= dx Ey
+    if constexpr (F == 5) { o0 -= (float)gy; o1 += (float)gx; }  // Hx -= dy Ez, Hy += dx Ez
+}
+
+// Flux of one face node from the jump d = q- - q+ (6 fields), the outward
+// normal and Fscale (h = Fscale/2, ah = alpha Fscale/2; both 0 on padding
+// rows).  R = float or double.
+template <typename R>
+__device__ __forceinline__ void face_flux(const R (&d)[6], R nx, R ny, R nz, R h, R ah, R (&fl)[6]) {
+    const R dHx = d[0], dHy = d[1], dHz = d[2], dEx = d[3], dEy = d[4], dEz = d[5];
+    const R ndH = nx * dHx + ny * dHy + nz * dHz;
+    const R ndE = nx * dEx + ny * dEy + nz * dEz;
+    const R cEx = ny * dEz - nz * dEy, cEy = nz * dEx - nx * dEz, cEz = nx * dEy - ny * dEx;
+    const R cHx = ny * dHz - nz * dHy, cHy = nz * dHx - nx * dHz, cHz = nx * dHy - ny * dHx;
+    fl[0] = h * cEx + ah * (nx * ndH - dHx);
+    fl[1] = h * cEy + ah * (ny * ndH - dHy);
+    fl[2] = h * cEz + ah * (nz * ndH - dHz);
+    fl[3] = -h * cHx + ah * (nx * ndE - dEx);
+    fl[4] = -h * cHy + ah * (ny * ndE - dEy);
+    fl[5] = -h * cHz + ah * (nz * ndE - dEz);
+}
 
 }  // namespace
 
-// Tuning: K-steps of face traces kept in flight, fields of volume operands
-// kept in flight.  One K-step of traces keeps the kernel within its 256
-// registers; with two, registers spill to scratch and the order-4 stage runs
-// 14 % slower.
+// Face nodes of partner traces kept in flight ahead of their use (FP32: one
+// face node per K step; split: eight per K step).
 #ifndef DGW_3D_SPD
-#define DGW_3D_SPD 1
+#define DGW_3D_SPD 2
 #endif
-#ifndef DGW_3D_VPD
-#define DGW_3D_VPD 1
+#ifndef DGW_3D_SPD_SPLIT
+#define DGW_3D_SPD_SPLIT 1
 #endif
-constexpr int SPD = DGW_3D_SPD;
-constexpr int VPD = DGW_3D_VPD;
 
-template <int N>
+template <int N, bool SPLIT>
 __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     using T = Tet<N>;
-    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, MT = T::MT, KV = T::KV, KL = T::KL;
-    constexpr int AV = T::AV, AL = T::AL, NT = T::NT;
-    __shared__ float sA[AV + AL];
+    constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, NPP = T::NPP, KV = T::KV, NC = T::NC, NR = T::NR;
+    constexpr int MTD = T::MTD, MTL = T::MTL, KL = T::KL, KVS = T::KVS, KLS = T::KLS, RS = T::RS, ES = T::ES;
+    constexpr int AV = T::AV, AL = T::AL, FV = T::FV, FL = T::FL, FT = T::FT, KT = T::KT, NT = T::NT;
+    constexpr int FRAG4 = SPLIT ? 2 * (FV + FL) + (FT + 3) / 4 : (AV + AL + 3) / 4;  // in 16-byte units
+    __shared__ uint4 sAq[FRAG4];
     __shared__ int stab[NT];
-    // each wave's copy of its 16 elements' fields, [field * Np + node][17]
-    // (row stride 17: rows of different lane groups fall in different banks);
-    // the face traces and the update read the element's own values here
-    // instead of from memory again
-    constexpr int FS = 17;
-    __shared__ float sF[8][6 * Np * FS];
+    // split: each wave's FP64 face data of its 16 elements, [element][face * 4 + q]
+    // (n_x, n_y, n_z, Fscale), read per face node
+    __shared__ double sfd[SPLIT ? 8 : 1][16][16];
+    // each wave's copy of its 16 elements' fields, [element][field][node],
+    // element stride ES
+    __shared__ __attribute__((aligned(16))) float sF[8][16 * ES];
+    const float *sA = reinterpret_cast<const float *>(sAq);
 
-    for (int i = threadIdx.x; i < AV + AL; i += 512) sA[i] = A.opsfrag[i];
-    for (int i = threadIdx.x; i < NT; i += 512) stab[i] = A.itab[i];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.opsfrag);
+        for (int i = threadIdx.x; i < FRAG4; i += 512) sAq[i] = src[i];
+        for (int i = threadIdx.x; i < NT; i += 512) stab[i] = A.itab[i];
+    }
     __syncthreads();
 
     const int lane0 = threadIdx.x & 63;
@@ -107,7 +208,6 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     const int x = blockIdx.x & 7, bi = blockIdx.x >> 3, GB = gridDim.x >> 3;
     const int q8 = npairs >> 3, r8 = npairs & 7;
     const int xbase = x * q8 + (x < r8 ? x : r8), xcount = q8 + (x < r8 ? 1 : 0);
-    const float ha = 0.5f * A.alpha;
 
     float *F = sF[w];
     for (int pl = bi; pl < xcount; pl += GB) {
@@ -120,305 +220,608 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
         asm volatile("" : "+v"(lane));
         const int g = lane >> 4, c = lane & 15;
         const int col = 16 * (w & 3) + c;
-        constexpr unsigned TB = 6 * Np * 64 * 4;  // bytes of a tile's fields
-        const __amdgpu_buffer_rsrc_t rq = rsrc(A.qin + (size_t)tile * (6 * Np * 64), TB);
-        const unsigned vcol = (unsigned)col * 4;             // column within a row
-        const unsigned vrow = (unsigned)(g * 64 + col) * 4;  // row 4 ks + g of a K-step
+        constexpr unsigned TB = 64 * RS * 4;  // bytes of a tile's fields
+        const __amdgpu_buffer_rsrc_t rq = rsrc(A.qin + (size_t)tile * (64 * RS), TB);
+        const unsigned vel = (unsigned)(col * RS) * 4;   // the lane's element
+        const unsigned v16 = vel + 16u * (unsigned)g;    // its first 16-byte run
+        const unsigned v4 = vel + 4u * (unsigned)g;      // its first single node
+        float *Fc = F + c * ES;
+        const unsigned vcol = (unsigned)col * 4;         // column of a tiled factor row
 
-        float G[9];
-        float cv[6][MT][4];
+        float cv[6][KV];  // volume part of the right-hand side, nodes of the lane
+#pragma unroll
+        for (int o = 0; o < 6; ++o)
+#pragma unroll
+            for (int i = 0; i < KV; ++i) cv[o][i] = 0.f;
+
         if (active) {
-        {
-            const __amdgpu_buffer_rsrc_t rg = rsrc(A.geo + (size_t)tile * (9 * 64), 9 * 64 * 4);
+            if constexpr (!SPLIT) {
+                // ---- FP32 volume: operands of field f are the lane's nodes
+                // (K row 4 ks + g = node slot ks); the next field's are in
+                // flight while field f is contracted
+                float G[9];
+                {
+                    const __amdgpu_buffer_rsrc_t rg = rsrc(A.geo + (size_t)tile * (9 * 64), 9 * 64 * 4);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) G[q] = bload(rg, vcol, q * 256);
-        }
-
-        // volume part of the right-hand side, in plain registers
-#pragma unroll
-        for (int f = 0; f < 6; ++f)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) cv[f][mt][jj] = 0.f;
-
-        // ---- volume: derivatives of field f, then their curl contributions
-        // operands of the next VPD fields in flight (a ring of registers);
-        // rows past Np belong to the next field (or lie past the tile, read
-        // as 0): their operator columns are zero, so they need no masking
-        float bring[VPD][KV];
-#pragma unroll
-        for (int f0 = 0; f0 < VPD; ++f0)
-#pragma unroll
-            for (int ks = 0; ks < KV; ++ks) bring[f0][ks] = bload(rq, vrow, (f0 * Np + 4 * ks) * 256);
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            float bq[KV];
-#pragma unroll
-            for (int ks = 0; ks < KV; ++ks) {
-                bq[ks] = bring[f % VPD][ks];
-                if (4 * ks + g < Np) F[(f * Np + 4 * ks + g) * FS + c] = bq[ks];
-            }
-            if (f + VPD < 6) {
-#pragma unroll
-                for (int ks = 0; ks < KV; ++ks) bring[f % VPD][ks] = bload(rq, vrow, ((f + VPD) * Np + 4 * ks) * 256);
-            }
-            floatx4 d[3][MT];
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) d[p][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-            // the operator fragments are re-read from LDS for every field: an
-            // index opaque to the compiler keeps it from holding all of them
-            // in registers across the six fields
-            int la = lane;
-            asm volatile("" : "+v"(la));
-#pragma unroll
-            for (int ks = 0; ks < KV; ++ks)
-#pragma unroll
-                for (int p = 0; p < 3; ++p)
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        d[p][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[((p * MT + mt) * KV + ks) * 64 + la],
-                                                                       bq[ks], d[p][mt], 0, 0, 0);
-            // chain rule: d_x u = r_x D_r u + s_x D_s u + t_x D_t u, ...
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const float dr = d[0][mt][jj], ds = d[1][mt][jj], dtt = d[2][mt][jj];
-                    const float gx = G[0] * dr + G[3] * ds + G[6] * dtt;
-                    const float gy = G[1] * dr + G[4] * ds + G[7] * dtt;
-                    const float gz = G[2] * dr + G[5] * ds + G[8] * dtt;
-                    // fields 0..5 = Hx, Hy, Hz, Ex, Ey, Ez
-                    if (f == 0) { cv[4][mt][jj] += gz; cv[5][mt][jj] -= gy; }  // Ey += dz Hx, Ez -= dy Hx
-                    if (f == 1) { cv[3][mt][jj] -= gz; cv[5][mt][jj] += gx; }  // Ex -= dz Hy, Ez += dx Hy
-                    if (f == 2) { cv[3][mt][jj] += gy; cv[4][mt][jj] -= gx; }  // Ex += dy Hz, Ey -= dx Hz
-                    if (f == 3) { cv[1][mt][jj] -= gz; cv[2][mt][jj] += gy; }  // Hy -= dz Ex, Hz += dy Ex
-                    if (f == 4) { cv[0][mt][jj] += gz; cv[2][mt][jj] -= gx; }  // Hx += dz Ey, Hz -= dx Ey
-                    if (f == 5) { cv[0][mt][jj] -= gy; cv[1][mt][jj] += gx; }  // Hx -= dy Ez, Hy += dx Ez
+                    for (int q = 0; q < 9; ++q) G[q] = bload(rg, vcol, q * 256);
                 }
-            // materialise the sums here: otherwise they are sunk to their use
-            // in the update and every field's derivatives stay live until then
+                auto load_b = [&](int f, float (&b)[KV]) {
 #pragma unroll
-            for (int o = 0; o < 6; ++o)
+                    for (int t = 0; t < NC; ++t) bload4(rq, v16, (f * NPP + 16 * t) * 4, &b[4 * t]);
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                    for (int r = 0; r < NR; ++r) b[4 * NC + r] = bload(rq, v4, (f * NPP + 16 * NC + 4 * r) * 4);
+                };
+                float bn[KV];
+                load_b(0, bn);
+                auto field = [&](auto FI) {
+                    constexpr int f = decltype(FI)::value;
+                    float b[KV];
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) asm volatile("" : "+v"(cv[o][mt][jj]));
-            __builtin_amdgcn_sched_barrier(0);
-        }
+                    for (int i = 0; i < KV; ++i) b[i] = bn[i];
+                    // the wave's LDS copy of field f
+#pragma unroll
+                    for (int t = 0; t < NC; ++t)
+                        *reinterpret_cast<floatx4 *>(Fc + f * NPP + 16 * t + 4 * g) =
+                            floatx4{b[4 * t], b[4 * t + 1], b[4 * t + 2], b[4 * t + 3]};
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) Fc[f * NPP + 16 * NC + 4 * r + g] = b[4 * NC + r];
+                    if constexpr (f + 1 < 6) load_b(f + 1, bn);
+                    floatx4 d[MTD];
+#pragma unroll
+                    for (int m = 0; m < MTD; ++m) d[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    // operator fragments re-read from LDS for every field (an
+                    // index opaque to the compiler keeps them out of registers)
+                    int la = lane;
+                    asm volatile("" : "+v"(la));
+#pragma unroll
+                    for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                        for (int m = 0; m < MTD; ++m)
+                            d[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[(m * KV + ks) * 64 + la], b[ks], d[m], 0, 0, 0);
+                    // chain rule: slot 3 i + p holds D_p of node slot i
+#pragma unroll
+                    for (int i = 0; i < KV; ++i) {
+                        const float dr = d[(3 * i) / 4][(3 * i) % 4], ds = d[(3 * i + 1) / 4][(3 * i + 1) % 4];
+                        const float dtt = d[(3 * i + 2) / 4][(3 * i + 2) % 4];
+                        const float gx = G[0] * dr + G[3] * ds + G[6] * dtt;
+                        const float gy = G[1] * dr + G[4] * ds + G[7] * dtt;
+                        const float gz = G[2] * dr + G[5] * ds + G[8] * dtt;
+                        curl_add<f>(gx, gy, gz, cv[0][i], cv[1][i], cv[2][i], cv[3][i], cv[4][i], cv[5][i]);
+                    }
+                    // materialise the sums here: otherwise they are sunk to
+                    // their use and every field's derivatives stay live
+#pragma unroll
+                    for (int o = 0; o < 6; ++o)
+#pragma unroll
+                        for (int i = 0; i < KV; ++i) asm volatile("" : "+v"(cv[o][i]));
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                field(std::integral_constant<int, 0>{});
+                field(std::integral_constant<int, 1>{});
+                field(std::integral_constant<int, 2>{});
+                field(std::integral_constant<int, 3>{});
+                field(std::integral_constant<int, 4>{});
+                field(std::integral_constant<int, 5>{});
+            } else {
+                // ---- split volume: K step ks, lane group g holds the nodes
+                // 32 ks + 8 g .. + 7 (two 16-byte runs; runs past the field
+                // meet zero operator columns and are not loaded)
+                double G[9];
+                {
+                    const double *gt = A.geo64 + (size_t)tile * (9 * 64);
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) G[q] = gt[(unsigned)(q * 64 + col)];
+                }
+                const unsigned v8 = vel + 32u * (unsigned)g;
+                constexpr int KTA = KT > 0 ? KT : 1;
+                // 16-bit K steps (b), then the FP32 tail: K row 4 kt + g of
+                // the tail is node 32 KVS + 4 kt + g (bt)
+                auto load_b = [&](int f, float (&b)[KVS][8], float (&bt)[KTA]) {
+#pragma unroll
+                    for (int ks = 0; ks < KVS; ++ks)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (32 * ks + 8 * g + 4 * h < NPP)
+                                bload4(rq, v8, (f * NPP + 32 * ks + 4 * h) * 4, &b[ks][4 * h]);
+                            else
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) b[ks][4 * h + k] = 0.f;
+                        }
+#pragma unroll
+                    for (int kt = 0; kt < KT; ++kt) bt[kt] = bload(rq, v4, (f * NPP + 32 * KVS + 4 * kt) * 4);
+                };
+                float bn[KVS][8], btn[KTA];
+                float qcn = bload(rq, vel, 0);
+                load_b(0, bn, btn);
+                auto field = [&](auto FI) {
+                    constexpr int f = decltype(FI)::value;
+                    float b[KVS][8], bt[KTA];
+                    const float qc = qcn;
+#pragma unroll
+                    for (int ks = 0; ks < KVS; ++ks)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) b[ks][q] = bn[ks][q];
+#pragma unroll
+                    for (int kt = 0; kt < KTA; ++kt) bt[kt] = btn[kt];
+#pragma unroll
+                    for (int ks = 0; ks < KVS; ++ks)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            if (32 * ks + 8 * g + 4 * h < NPP)
+                                *reinterpret_cast<floatx4 *>(Fc + f * NPP + 32 * ks + 8 * g + 4 * h) =
+                                    floatx4{b[ks][4 * h], b[ks][4 * h + 1], b[ks][4 * h + 2], b[ks][4 * h + 3]};
+#pragma unroll
+                    for (int kt = 0; kt < KT; ++kt) Fc[f * NPP + 32 * KVS + 4 * kt + g] = bt[kt];
+                    if constexpr (f + 1 < 6) {
+                        qcn = bload(rq, vel, (f + 1) * NPP * 4);
+                        load_b(f + 1, bn, btn);
+                    }
+                    floatx4 d[MTD];
+#pragma unroll
+                    for (int m = 0; m < MTD; ++m) d[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    int la = lane;
+                    asm volatile("" : "+v"(la));
+#pragma unroll
+                    for (int ks = 0; ks < KVS; ++ks) {
+                        bf16x8 bh, bl;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const float v = b[ks][q] - qc;
+                            const __bf16 hh = (__bf16)v;
+                            bh[q] = hh;
+                            bl[q] = (__bf16)(v - (float)hh);
+                        }
+#pragma unroll
+                        for (int m = 0; m < MTD; ++m) {
+                            const int fi = (m * KVS + ks) * 64 + la;
+                            d[m] = mfma3(as_bf16x8(sAq[fi]), as_bf16x8(sAq[FV + FL + fi]), bh, bl, d[m]);
+                        }
+                    }
+                    const float *sT = reinterpret_cast<const float *>(sAq + 2 * (FV + FL));
+#pragma unroll
+                    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                        for (int m = 0; m < MTD; ++m)
+                            d[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(sT[(m * KT + kt) * 64 + la], bt[kt] - qc, d[m], 0, 0,
+                                                                        0);
+                    // chain rule and curl in FP64 with the FP64 factors
+#pragma unroll
+                    for (int i = 0; i < KV; ++i) {
+                        const double dr = d[(3 * i) / 4][(3 * i) % 4], ds = d[(3 * i + 1) / 4][(3 * i + 1) % 4];
+                        const double dtt = d[(3 * i + 2) / 4][(3 * i + 2) % 4];
+                        const double gx = G[0] * dr + G[3] * ds + G[6] * dtt;
+                        const double gy = G[1] * dr + G[4] * ds + G[7] * dtt;
+                        const double gz = G[2] * dr + G[5] * ds + G[8] * dtt;
+                        curl_add<f>(gx, gy, gz, cv[0][i], cv[1][i], cv[2][i], cv[3][i], cv[4][i], cv[5][i]);
+                    }
+#pragma unroll
+                    for (int o = 0; o < 6; ++o)
+#pragma unroll
+                        for (int i = 0; i < KV; ++i) asm volatile("" : "+v"(cv[o][i]));
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                field(std::integral_constant<int, 0>{});
+                field(std::integral_constant<int, 1>{});
+                field(std::integral_constant<int, 2>{});
+                field(std::integral_constant<int, 3>{});
+                field(std::integral_constant<int, 4>{});
+                field(std::integral_constant<int, 5>{});
+            }
         }  // active
+
+        // ---- surface.  Face records of the element, held as scalars
+        // (selected per lane, no per-lane array indexing)
+        int rc0 = -1, rc1 = -1, rc2 = -1, rc3 = -1;
+        if (active) {
+            const __amdgpu_buffer_rsrc_t rn = rsrc(A.nbr + (size_t)tile * (4 * 64), 4 * 64 * 4);
+            rc0 = __builtin_bit_cast(int, bload(rn, vcol, 0));
+            rc1 = __builtin_bit_cast(int, bload(rn, vcol, 256));
+            rc2 = __builtin_bit_cast(int, bload(rn, vcol, 512));
+            rc3 = __builtin_bit_cast(int, bload(rn, vcol, 768));
+        }
+        auto face_rec = [&](int face) { return face == 0 ? rc0 : face == 1 ? rc1 : face == 2 ? rc2 : rc3; };
+        // all partner traces outside the pair through one resource over the
+        // field array
+        const __amdgpu_buffer_rsrc_t rall = rsrc(A.qin, (unsigned)A.ntiles * TB);
+        // where the partner trace of face node j lives: element e2, node pn;
+        // on the wall the element itself (the mirror sign is applied with the
+        // jump); inpair: e2 lies in this pair of tiles (LDS copy)
+        struct Partner {
+            int own, e2, pn;
+            bool wall, inpair;
+        };
+        auto partner = [&](int j) {
+            Partner P;
+            const int jc = j < Nafp ? j : Nafp - 1;  // padding rows read a valid node
+            const int face = jc / Nfp, i = jc - face * Nfp;
+            P.own = stab[jc];
+            const int rc = face_rec(face);
+            P.wall = rc < 0;
+            P.e2 = P.wall ? tile * 64 + col : (rc >> 5);
+            P.pn = P.wall ? P.own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
+            P.inpair = (unsigned)((P.e2 >> 6) - 2 * pair) < 2u;
+            return P;
+        };
+        // partner traces outside the pair are gathered from memory SPD face
+        // nodes ahead of their use (the first ones across the barrier below)
+        auto gather = [&](int j, float (&pb)[6]) {
+            const Partner P = partner(j);
+            if (!P.inpair) {
+                const unsigned vp = ((unsigned)P.e2 * RS + P.pn) * 4;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pb[f] = bload(rall, vp, f * NPP * 4);
+            }
+        };
+        // own and partner traces of face node j (partner from the ring
+        // slot pb when it lies outside the pair)
+        auto traces = [&](int j, const float (&pb)[6], float (&m)[6], float (&pv)[6]) {
+            const Partner P = partner(j);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) m[f] = Fc[f * NPP + P.own];
+            if (P.inpair) {
+                const int t2 = (P.e2 >> 6) - 2 * pair;
+                const float *F2 = sF[4 * t2 + ((P.e2 & 63) >> 4)] + (P.e2 & 15) * ES;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pv[f] = F2[f * NPP + P.pn];
+            } else {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pv[f] = pb[f];
+            }
+            return P.wall;
+        };
+        // face node of this lane at slot t: FP32 one per K step (4 ks + g),
+        // split eight per K step (32 ks + 8 g + q)
+        constexpr int NS = SPLIT ? 8 * KLS : KL;
+        constexpr int SPD = SPLIT ? DGW_3D_SPD_SPLIT : DGW_3D_SPD;
+        auto slot_j = [&](int t) { return SPLIT ? 32 * (t / 8) + 8 * g + t % 8 : 4 * t + g; };
+        float ring[SPD][6];
+#pragma unroll
+        for (int t = 0; t < SPD; ++t)
+#pragma unroll
+            for (int f = 0; f < 6; ++f) ring[t][f] = 0.f;
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < SPD; ++t)
+                if (t < NS) gather(slot_j(t), ring[t]);
+        }
         // every wave's LDS copy of its fields is complete: partner traces of
         // elements in this pair of tiles are read from there
         __syncthreads();
         if (active) {
+            // the LIFT contraction accumulates on top of the volume part:
+            // slot 4 mt + jj of lane group g = node slot i
+            floatx4 acc[6][MTL];
+#pragma unroll
+            for (int o = 0; o < 6; ++o)
+#pragma unroll
+                for (int mt = 0; mt < MTL; ++mt)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        constexpr int dummy = 0;
+                        const int i = 4 * mt + jj;
+                        acc[o][mt][jj] = i < KV ? cv[o][i < KV ? i : dummy] : 0.f;
+                    }
 
-        // ---- surface: flux at face node j = 4 ks + g, then LIFT.  The face
-        // records and face data of the element are loaded once, up front, and
-        // held as scalars (selected per lane, no per-lane array indexing): a
-        // load whose value is needed in the same step would make the step
-        // wait for every load issued before it, prefetched traces included
-        const __amdgpu_buffer_rsrc_t rn = rsrc(A.nbr + (size_t)tile * (4 * 64), 4 * 64 * 4);
-        const __amdgpu_buffer_rsrc_t rf = rsrc(A.fgeo + (size_t)tile * (16 * 64), 16 * 64 * 4);
-        const int rc0 = __builtin_bit_cast(int, bload(rn, vcol, 0)), rc1 = __builtin_bit_cast(int, bload(rn, vcol, 256));
-        const int rc2 = __builtin_bit_cast(int, bload(rn, vcol, 512)), rc3 = __builtin_bit_cast(int, bload(rn, vcol, 768));
-        float fd[16];
+            if constexpr (!SPLIT) {
+                float fd[16];
+                {
+                    const __amdgpu_buffer_rsrc_t rf = rsrc(A.fgeo + (size_t)tile * (16 * 64), 16 * 64 * 4);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) fd[q] = bload(rf, vcol, q * 256);
-        auto face_rec = [&](int face) { return face == 0 ? rc0 : face == 1 ? rc1 : face == 2 ? rc2 : rc3; };
-        auto face_val = [&](int face, int q) {
-            return face == 0 ? fd[q] : face == 1 ? fd[4 + q] : face == 2 ? fd[8 + q] : fd[12 + q];
-        };
-        // all partner traces through one resource over the field array
-        const __amdgpu_buffer_rsrc_t rall = rsrc(A.qin, (unsigned)A.ntiles * TB);
-        // own and partner traces of face node j (on the wall the partner is
-        // the element itself; the mirror sign is applied with the jump)
-        auto load_traces = [&](int ks, float (&m)[6], float (&pv)[6], int &wall) {
-            const int j = 4 * ks + g;
-            const int jc = j < Nafp ? j : Nafp - 1;  // lanes past the faces read a valid node
-            const int face = jc / Nfp, i = jc - face * Nfp;
-            const int own = stab[jc];
-            const int rc = face_rec(face);
-            wall = rc < 0;
-            const int e2 = wall ? tile * 64 + col : (rc >> 5);
-            const int pn = wall ? own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
-            const unsigned vp = (((unsigned)(e2 >> 6) * (6 * Np) + pn) * 64 + (e2 & 63)) * 4;
-            const int t2 = (e2 >> 6) - 2 * pair;  // partner tile within the pair?
+                    for (int q = 0; q < 16; ++q) fd[q] = bload(rf, vcol, q * 256);
+                }
+                auto face_val = [&](int face, int q) {
+                    return face == 0 ? fd[q] : face == 1 ? fd[4 + q] : face == 2 ? fd[8 + q] : fd[12 + q];
+                };
+                const float ha = 0.5f * A.alpha;
+                // FP32 LIFT, K step ks: lane group g evaluates face node 4 ks + g
 #pragma unroll
-            for (int f = 0; f < 6; ++f) m[f] = F[(f * Np + own) * FS + c];
-            if ((unsigned)t2 < 2u) {
-                const float *F2 = sF[4 * t2 + ((e2 & 63) >> 4)];
+                for (int ks = 0; ks < KL; ++ks) {
+                    const int j = 4 * ks + g;
+                    float m[6], pv[6];
+                    const bool wall = traces(j, ring[ks % SPD], m, pv);
+                    if (ks + SPD < KL) gather(slot_j(ks + SPD), ring[ks % SPD]);
+                    const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
+                    float dq[6];
 #pragma unroll
-                for (int f = 0; f < 6; ++f) pv[f] = F2[(f * Np + pn) * FS + (e2 & 15)];
+                    for (int f = 0; f < 6; ++f) dq[f] = m[f] - ((wall && f >= 3) ? -pv[f] : pv[f]);
+                    const float fs = face_val(face, 3);
+                    const float h = j < Nafp ? 0.5f * fs : 0.f, ah = j < Nafp ? ha * fs : 0.f;
+                    float fl[6];
+                    face_flux<float>(dq, face_val(face, 0), face_val(face, 1), face_val(face, 2), h, ah, fl);
+#pragma unroll
+                    for (int mt = 0; mt < MTL; ++mt) {
+                        const float a = sA[AV + (mt * KL + ks) * 64 + lane];
+#pragma unroll
+                        for (int f = 0; f < 6; ++f)
+                            acc[f][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, fl[f], acc[f][mt], 0, 0, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             } else {
+                {
+                    // lane group g fetches face g of its element
+                    const double *ft = A.fgeo64 + (size_t)tile * (16 * 64);
 #pragma unroll
-                for (int f = 0; f < 6; ++f) pv[f] = bload(rall, vp, f * Np * 256);
+                    for (int q = 0; q < 4; ++q) sfd[w][c][4 * g + q] = ft[(unsigned)((4 * g + q) * 64 + col)];
+                }
+                auto face_val = [&](int face, int q) { return sfd[w][c][4 * face + q]; };
+                const double ha = 0.5 * (double)A.alpha;
+                // split LIFT, K step ks: lane group g evaluates face nodes
+                // 32 ks + 8 g + q, q = 0..7
+#pragma unroll
+                for (int ks = 0; ks < KLS; ++ks) {
+                    // hi and lo parts of the flux rows, two BF16 per word
+                    unsigned bhw[6][4], blw[6][4];
+#pragma unroll
+                    for (int q2 = 0; q2 < 4; ++q2) {
+                        float fl2[2][6];
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int t = 8 * ks + 2 * q2 + u;
+                            const int j = 32 * ks + 8 * g + 2 * q2 + u;
+                            float m[6], pv[6];
+                            const bool wall = traces(j, ring[t % SPD], m, pv);
+                            if (t + SPD < NS) gather(slot_j(t + SPD), ring[t % SPD]);
+                            const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
+                            double dq[6];
+#pragma unroll
+                            for (int f = 0; f < 6; ++f)
+                                dq[f] = (double)m[f] - ((wall && f >= 3) ? -(double)pv[f] : (double)pv[f]);
+                            const double fs = face_val(face, 3);
+                            const double h = j < Nafp ? 0.5 * fs : 0.0, ah = j < Nafp ? ha * fs : 0.0;
+                            double fl[6];
+                            face_flux<double>(dq, face_val(face, 0), face_val(face, 1), face_val(face, 2), h, ah, fl);
+#pragma unroll
+                            for (int f = 0; f < 6; ++f) fl2[u][f] = (float)fl[f];
+                        }
+#pragma unroll
+                        for (int f = 0; f < 6; ++f) {
+                            const bf16x2 hh = __builtin_convertvector((float2v){fl2[0][f], fl2[1][f]}, bf16x2);
+                            const bf16x2 ll = __builtin_convertvector(
+                                (float2v){fl2[0][f] - (float)hh[0], fl2[1][f] - (float)hh[1]}, bf16x2);
+                            bhw[f][q2] = __builtin_bit_cast(unsigned, hh);
+                            blw[f][q2] = __builtin_bit_cast(unsigned, ll);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MTL; ++mt) {
+                        const int fi = FV + (mt * KLS + ks) * 64 + lane;
+                        const bf16x8 ah16 = as_bf16x8(sAq[fi]), al16 = as_bf16x8(sAq[FV + FL + fi]);
+#pragma unroll
+                        for (int f = 0; f < 6; ++f) {
+                            const uint4 hu = {bhw[f][0], bhw[f][1], bhw[f][2], bhw[f][3]};
+                            const uint4 lu = {blw[f][0], blw[f][1], blw[f][2], blw[f][3]};
+                            acc[f][mt] = mfma3(ah16, al16, as_bf16x8(hu), as_bf16x8(lu), acc[f][mt]);
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
-        };
-        // the LIFT contraction accumulates on top of the volume part
-        floatx4 acc[6][MT];
-#pragma unroll
-        for (int f = 0; f < 6; ++f)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                acc[f][mt] = floatx4{cv[f][mt][0], cv[f][mt][1], cv[f][mt][2], cv[f][mt][3]};
-        // traces of the next SPD K-steps in flight (a ring of registers)
-        float mb[SPD][6], pb[SPD][6];
-        int wb[SPD];
-#pragma unroll
-        for (int s0 = 0; s0 < SPD; ++s0)
-            if (s0 < KL) load_traces(s0, mb[s0], pb[s0], wb[s0]);
-#pragma unroll
-        for (int ks = 0; ks < KL; ++ks) {
-            float m[6], pv[6];
-            const int slot = ks % SPD;
+
+            // ---- fused low-storage RK update of the lane's nodes: every
+            // residual load first (their latencies overlap), then per field
+            // the arithmetic and the stores
+            const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (64 * RS), TB);
+            const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (64 * RS), TB);
+            float rv[6][KV];
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                m[f] = mb[slot][f];
-                pv[f] = pb[slot][f];
+#pragma unroll
+                for (int t = 0; t < NC; ++t) bload4(rr, v16, (f * NPP + 16 * t) * 4, &rv[f][4 * t]);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) rv[f][4 * NC + r] = bload(rr, v4, (f * NPP + 16 * NC + 4 * r) * 4);
             }
-            const int wall = wb[slot];
-            if (ks + SPD < KL) load_traces(ks + SPD, mb[slot], pb[slot], wb[slot]);
-            const int j = 4 * ks + g;
-            const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
-            // [q] = q- - q+, with q+ = (H-, -E-) on the wall
-            float d[6];
 #pragma unroll
-            for (int f = 0; f < 6; ++f) d[f] = m[f] - ((wall && f >= 3) ? -pv[f] : pv[f]);
-            const float nx = face_val(face, 0), ny = face_val(face, 1);
-            const float nz = face_val(face, 2), fs = face_val(face, 3);
-            const float dHx = d[0], dHy = d[1], dHz = d[2], dEx = d[3], dEy = d[4], dEz = d[5];
-            const float ndH = nx * dHx + ny * dHy + nz * dHz;
-            const float ndE = nx * dEx + ny * dEy + nz * dEz;
-            const float h = j < Nafp ? 0.5f * fs : 0.f, ah = j < Nafp ? ha * fs : 0.f;
-            const float cEx = ny * dEz - nz * dEy, cEy = nz * dEx - nx * dEz, cEz = nx * dEy - ny * dEx;
-            const float cHx = ny * dHz - nz * dHy, cHy = nz * dHx - nx * dHz, cHz = nx * dHy - ny * dHx;
-            float fl[6];
-            fl[0] = h * cEx + ah * (nx * ndH - dHx);
-            fl[1] = h * cEy + ah * (ny * ndH - dHy);
-            fl[2] = h * cEz + ah * (nz * ndH - dHz);
-            fl[3] = -h * cHx + ah * (nx * ndE - dEx);
-            fl[4] = -h * cHy + ah * (ny * ndE - dEy);
-            fl[5] = -h * cHz + ah * (nz * ndE - dEz);
+            for (int f = 0; f < 6; ++f) {
+                float qv[KV];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const float a = sA[AV + (mt * KL + ks) * 64 + lane];
+                for (int t = 0; t < NC; ++t) {
+                    const floatx4 q4 = *reinterpret_cast<const floatx4 *>(Fc + f * NPP + 16 * t + 4 * g);
 #pragma unroll
-                for (int f = 0; f < 6; ++f) acc[f][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, fl[f], acc[f][mt], 0, 0, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-
-        // ---- fused low-storage RK update
-        const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (6 * Np * 64), TB);
-        const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (6 * Np * 64), TB);
-        const unsigned vout = (unsigned)(4 * g * 64 + col) * 4;  // row 16 mt + 4 g + jj
-        // per field: all loads, then all arithmetic, then the stores (a store
-        // between two loads orders them and exposes one memory latency per
-        // value).  Rows 16 mt + 4 g + jj >= Np read the next field's rows (or
-        // 0 past the tile) and are not stored.
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            float rv[MT][4], qv[MT][4];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const unsigned so = (f * Np + 16 * mt + jj) * 256;
-                    rv[mt][jj] = bload(rr, vout, so);
-                    const int n = 16 * mt + 4 * g + jj;
-                    qv[mt][jj] = n < Np ? F[(f * Np + n) * FS + c] : 0.f;
+                    for (int k = 0; k < 4; ++k) qv[4 * t + k] = q4[k];
                 }
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+                for (int r = 0; r < NR; ++r) qv[4 * NC + r] = Fc[f * NPP + 16 * NC + 4 * r + g];
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    rv[mt][jj] = A.a * rv[mt][jj] + A.dt * acc[f][mt][jj];
-                    qv[mt][jj] = qv[mt][jj] + A.b * rv[mt][jj];
+                for (int i = 0; i < KV; ++i) {
+                    rv[f][i] = A.a * rv[f][i] + A.dt * acc[f][i / 4][i % 4];
+                    qv[i] = qv[i] + A.b * rv[f][i];
                 }
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+                for (int t = 0; t < NC; ++t) {
+                    bstore4(rr, &rv[f][4 * t], v16, (f * NPP + 16 * t) * 4);
+                    bstore4(ro, &qv[4 * t], v16, (f * NPP + 16 * t) * 4);
+                }
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    if (16 * mt + 4 * g + jj < Np) {
-                        const unsigned so = (f * Np + 16 * mt + jj) * 256;
-                        bstore(rr, rv[mt][jj], vout, so);
-                        bstore(ro, qv[mt][jj], vout, so);
+                for (int r = 0; r < NR; ++r)
+                    if (16 * NC + 4 * r + g < Np) {  // pad nodes stay 0
+                        bstore(rr, rv[f][4 * NC + r], v4, (f * NPP + 16 * NC + 4 * r) * 4);
+                        bstore(ro, qv[4 * NC + r], v4, (f * NPP + 16 * NC + 4 * r) * 4);
                     }
-                }
-        }
+            }
         }  // active
         __syncthreads();  // the LDS copies are read by other waves until here
     }
 }
 
-template <int N>
+template <int N, bool SPLIT>
 static hipError_t launch3d(const StageArgs &a, hipStream_t s) {
     // every pointer the kernel dereferences must be set
-    if (!a.opsfrag || !a.itab || !a.qin || !a.qout || !a.res || !a.geo || !a.fgeo || !a.nbr || a.ntiles <= 0 ||
-        a.ngroups < 8 || (a.ngroups & 7))
+    if (!a.opsfrag || !a.itab || !a.qin || !a.qout || !a.res || !a.nbr || a.ntiles <= 0 || a.ngroups < 8 ||
+        (a.ngroups & 7))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage3d_kernel<N>), dim3(a.ngroups), dim3(512), 0, s, a);
+    if (SPLIT ? (!a.geo64 || !a.fgeo64) : (!a.geo || !a.fgeo)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((stage3d_kernel<N, SPLIT>), dim3(a.ngroups), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, bool SPLIT>
 static int occupancy3d() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage3d_kernel<N>, 512, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage3d_kernel<N, SPLIT>, 512, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
 int blocks_per_cu_3d(int N) {
     switch (N) {
-        case 1: return occupancy3d<1>();
-        case 2: return occupancy3d<2>();
-        case 3: return occupancy3d<3>();
-        case 4: return occupancy3d<4>();
+        case 1: return occupancy3d<1, false>();
+        case 2: return occupancy3d<2, false>();
+        case 3: return occupancy3d<3, false>();
+        case 4: return occupancy3d<4, false>();
+        default: return 1;
+    }
+}
+
+int blocks_per_cu_3d_split(int N) {
+    switch (N) {
+        case 1: return occupancy3d<1, true>();
+        case 2: return occupancy3d<2, true>();
+        case 3: return occupancy3d<3, true>();
+        case 4: return occupancy3d<4, true>();
         default: return 1;
     }
 }
 
 hipError_t launch_stage3d(int N, const StageArgs &a, hipStream_t s) {
     switch (N) {
-        case 1: return launch3d<1>(a, s);
-        case 2: return launch3d<2>(a, s);
-        case 3: return launch3d<3>(a, s);
-        case 4: return launch3d<4>(a, s);
+        case 1: return launch3d<1, false>(a, s);
+        case 2: return launch3d<2, false>(a, s);
+        case 3: return launch3d<3, false>(a, s);
+        case 4: return launch3d<4, false>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stage3d_split(int N, const StageArgs &a, hipStream_t s) {
+    switch (N) {
+        case 1: return launch3d<1, true>(a, s);
+        case 2: return launch3d<2, true>(a, s);
+        case 3: return launch3d<3, true>(a, s);
+        case 4: return launch3d<4, true>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 const char *stage3d_kernel_name(int N) {
     (void)N;
-    return "stage3d_kernel<N>";
+    return "stage3d_kernel<N, false>";
 }
 
-// A-fragment order of the 3D kernel's operators: first Dr, Ds, Dt
-// (out[((p*MT + mt)*KV + ks)*64 + l] = D_p[16 mt + l%16][4 ks + l/16]), then
-// LIFT (out[AV + (mt*KL + ks)*64 + l] = LIFT[16 mt + l%16][4 ks + l/16]);
-// zero outside the matrices.  Returns the number of floats.
+namespace {
+
+// Output slot of row r (0..15) of M-tile mt: lane group r / 4, slot
+// 4 mt + r % 4.
+struct OutSlot {
+    int g, s;
+};
+inline OutSlot out_slot(int mt, int r) { return {r / 4, 4 * mt + r % 4}; }
+
+uint16_t bf16_bits(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // nearest even (finite inputs)
+}
+float bf16_value(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Entry of the packed derivative operator at output slot (g, s) and node
+// column n (0 outside): D_(s mod 3)[node of slot s / 3][n].
+double deriv_entry(int N, const double *const D[3], int g, int s, int n) {
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, KV = npp3d(Np) / 4;
+    if (s >= 3 * KV) return 0.0;
+    const int no = slot_node(KV, g, s / 3);
+    return (no < Np && n >= 0 && n < Np) ? D[s % 3][(size_t)no * Np + n] : 0.0;
+}
+// Entry of the row-permuted LIFT at output slot (g, s) and face node j.
+double lift_entry(int N, const double *LIFT, int g, int s, int j) {
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, KV = npp3d(Np) / 4, Nafp = 2 * (N + 1) * (N + 2);
+    if (s >= KV) return 0.0;
+    const int no = slot_node(KV, g, s);
+    return (no < Np && j < Nafp) ? LIFT[(size_t)no * Nafp + j] : 0.0;
+}
+
+}  // namespace
+
+// A-fragment order of the FP32 3D kernel's operators: the packed derivative
+// operator, out[(mt*KV + ks)*64 + l] = row (mt, l % 16), K row 4 ks + l / 16
+// (= node slot_node(KV, l / 16 % 4, ks)), then LIFT,
+// out[AV + (mt*KL + ks)*64 + l] = row (mt, l % 16), face node 4 ks + l / 16.
+// Returns the number of floats.
 int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, float *out) {
-    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 4 * ((N + 1) * (N + 2) / 2);
-    const int MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nafp + 3) / 4;
-    const int AV = 3 * MT * KV * 64, AL = MT * KL * 64;
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 2 * (N + 1) * (N + 2);
+    const int KV = npp3d(Np) / 4, MTD = (3 * KV + 3) / 4, MTL = (KV + 3) / 4, KL = (Nafp + 3) / 4;
+    const int AV = MTD * KV * 64, AL = MTL * KL * 64;
     if (!out) return AV + AL;
     const double *D[3] = {Dr, Ds, Dt};
-    for (int p = 0; p < 3; ++p)
-        for (int mt = 0; mt < MT; ++mt)
-            for (int ks = 0; ks < KV; ++ks)
-                for (int l = 0; l < 64; ++l) {
-                    const int row = 16 * mt + (l % 16), k = 4 * ks + l / 16;
-                    out[((p * MT + mt) * KV + ks) * 64 + l] = (row < Np && k < Np) ? (float)D[p][row * Np + k] : 0.f;
-                }
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MTD; ++mt)
+        for (int ks = 0; ks < KV; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const OutSlot o = out_slot(mt, l % 16);
+                const int kg = l / 16;  // K row 4 ks + kg: node of slot ks of lane group kg
+                out[(mt * KV + ks) * 64 + l] = (float)deriv_entry(N, D, o.g, o.s, slot_node(KV, kg, ks));
+            }
+    for (int mt = 0; mt < MTL; ++mt)
         for (int ks = 0; ks < KL; ++ks)
             for (int l = 0; l < 64; ++l) {
-                const int row = 16 * mt + (l % 16), k = 4 * ks + l / 16;
-                out[AV + (mt * KL + ks) * 64 + l] = (row < Np && k < Nafp) ? (float)LIFT[row * Nafp + k] : 0.f;
+                const OutSlot o = out_slot(mt, l % 16);
+                out[AV + (mt * KL + ks) * 64 + l] = (float)lift_entry(N, LIFT, o.g, o.s, 4 * ks + l / 16);
             }
     return AV + AL;
+}
+
+// Split operator fragments of the split 3D kernel, hi part then lo part,
+// each [derivative blocks (mt, ks)][LIFT blocks (mt, ks)] x 64 lanes x 8
+// BF16: lane l of block (mt, ks) holds row (mt, l % 16) at K rows
+// 32 ks + 8 (l / 16) + q, q = 0..7 (derivative: node columns in node order;
+// LIFT: face nodes).  Returns the size in bytes (out == nullptr: size only).
+int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, void *out) {
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 2 * (N + 1) * (N + 2), NPP = npp3d(Np);
+    const int KV = NPP / 4, MTD = (3 * KV + 3) / 4, MTL = (KV + 3) / 4;
+    const int TAILN = NPP % 32;
+    const bool tail = NPP >= 32 && TAILN > 0 && TAILN <= 8;
+    const int KVS = tail ? NPP / 32 : (NPP + 31) / 32, KT = tail ? TAILN / 4 : 0, KLS = (Nafp + 31) / 32;
+    const int FV = MTD * KVS * 64, FL = MTL * KLS * 64, FT = MTD * KT * 64;
+    const size_t total = (size_t)2 * (FV + FL) * 16 + (size_t)FT * 4;
+    if (!out) return (int)total;
+    uint16_t *o16 = static_cast<uint16_t *>(out);
+    const size_t lo_off = (size_t)(FV + FL) * 8;
+    auto put = [&](size_t frag, double v, int q) {
+        const uint16_t hi = bf16_bits((float)v);
+        const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
+        o16[frag * 8 + q] = hi;
+        o16[lo_off + frag * 8 + q] = lo;
+    };
+    const double *D[3] = {Dr, Ds, Dt};
+    for (int mt = 0; mt < MTD; ++mt)
+        for (int ks = 0; ks < KVS; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const OutSlot o = out_slot(mt, l % 16);
+                for (int q = 0; q < 8; ++q)
+                    put((size_t)(mt * KVS + ks) * 64 + l, deriv_entry(N, D, o.g, o.s, 32 * ks + 8 * (l / 16) + q), q);
+            }
+    for (int mt = 0; mt < MTL; ++mt)
+        for (int ks = 0; ks < KLS; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const OutSlot o = out_slot(mt, l % 16);
+                for (int q = 0; q < 8; ++q)
+                    put((size_t)FV + (mt * KLS + ks) * 64 + l, lift_entry(N, LIFT, o.g, o.s, 32 * ks + 8 * (l / 16) + q),
+                        q);
+            }
+    // FP32 tail of the derivative: row (mt, l % 16), K row 4 kt + l / 16 =
+    // node 32 KVS + 4 kt + l / 16
+    float *t32 = reinterpret_cast<float *>(static_cast<char *>(out) + (size_t)2 * (FV + FL) * 16);
+    for (int mt = 0; mt < MTD; ++mt)
+        for (int kt = 0; kt < KT; ++kt)
+            for (int l = 0; l < 64; ++l) {
+                const OutSlot o = out_slot(mt, l % 16);
+                t32[(mt * KT + kt) * 64 + l] = (float)deriv_entry(N, D, o.g, o.s, 32 * KVS + 4 * kt + l / 16);
+            }
+    return (int)total;
 }
 
 }  // namespace dgw

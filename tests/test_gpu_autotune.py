@@ -3,12 +3,39 @@ the state is restored bitwise, the choice is the fastest candidate, and a
 tuned solver computes bitwise what an untuned solver of the chosen kernel
 computes (per-element arithmetic does not depend on the launch shape).
 Different kernels may round differently, so the comparison is made from the
-fields at the tuning point on."""
+fields at the tuning point on.  Each tuned solve is also compared with the
+FP64 oracle: random fields, tuning, then steps at the CFL step, against the
+oracle's steps from the same fields (relative L2 within 1e-5 for FP32, 1e-4
+for split-BF16, 1e-12 for FP64)."""
 
 import numpy as np
 import pytest
 
+import oracle
+from oracle.maxwell import cfl_dt
 from paper_1304_5546_amd import dgw, inputs
+
+ORACLE_TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "fp64": 1e-12}
+
+
+def _tuned_vs_oracle(m, N, steps, **kw):
+    if m.dim == 2:
+        d = oracle.Discretization2D(m.vx, m.vy, m.elem_verts, N)
+        op = oracle.Maxwell2D(d)
+    else:
+        d = oracle.Discretization3D(m.vx, m.vy, m.vz, m.elem_verts, N)
+        op = oracle.Maxwell3D(d)
+    dt = cfl_dt(d, N)
+    q = np.random.default_rng(11).standard_normal((3 if m.dim == 2 else 6, d.K, d.Np)) * 0.1
+    want = op.run(q, dt, steps)
+    with dgw.Solver(m, N, **kw) as s:
+        s.set_fields(q)
+        t = s.autotune(stages=5)
+        s.advance_steps(steps, dt)
+        got = s.get_fields()
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    print(f"tuned {kw} (kernel {t['kernel']} x{t['groups_per_cu']}) vs oracle after {steps} steps: {err:.2e}")
+    assert err < ORACLE_TOL[kw.get("prec", "fp32")]
 
 pytestmark = pytest.mark.gpu
 
@@ -45,18 +72,26 @@ def _check_tuned(m, N, steps, **kw):
 
 
 def test_autotune_fp32_2d():
-    t = _check_tuned(inputs.tri_grid(48, seed=3, permute=True), 5, 10)
+    m = inputs.tri_grid(48, seed=3, permute=True)
+    t = _check_tuned(m, 5, 10)
     kernels = {c["kernel"] for c in t["tried"]}
     assert kernels == {1, 2, 3}
+    _tuned_vs_oracle(m, 5, 10)
 
 
 def test_autotune_fp64_2d():
-    t = _check_tuned(inputs.tri_grid(32, seed=4, permute=True), 4, 10, prec="fp64")
+    m = inputs.tri_grid(32, seed=4, permute=True)
+    t = _check_tuned(m, 4, 10, prec="fp64")
     assert {c["kernel"] for c in t["tried"]} == {1, 3}
+    _tuned_vs_oracle(m, 4, 10, prec="fp64")
 
 
 def test_autotune_split_and_3d_vary_the_launch_shape_only():
-    t = _check_tuned(inputs.tri_grid(40, seed=5), 5, 6, prec="split_bf16")
+    m = inputs.tri_grid(40, seed=5)
+    t = _check_tuned(m, 5, 6, prec="split_bf16")
     assert len({c["kernel"] for c in t["tried"]}) == 1
-    t = _check_tuned(inputs.tet_grid(6, seed=2), 3, 4)
+    _tuned_vs_oracle(m, 5, 6, prec="split_bf16")
+    m3 = inputs.tet_grid(6, seed=2)
+    t = _check_tuned(m3, 3, 4)
     assert len({c["kernel"] for c in t["tried"]}) == 1
+    _tuned_vs_oracle(m3, 3, 4)
