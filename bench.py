@@ -189,7 +189,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel", type=int, default=0,
-                    help="2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-operand MFMA, 3 derivative-first MFMA")
+                    help="2D stage kernel: 0 auto, 1 scalar-operand VALU, 2 fused-operand MFMA, 3 derivative-first MFMA, "
+                         "4 element-major MFMA")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "split_bf16", "split_fp16", "fp64"],
                     help="arithmetic of the timed path (value and roofline)")
     ap.add_argument("--autotune", action="store_true",
@@ -289,7 +290,8 @@ def main():
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
         kname = {1: f"stage2d_kernel<float, {N}, false>",
-                 3: f"stage2d_df_kernel<float, {N}, false, 1>"}.get(variant,
+                 3: f"stage2d_df_kernel<float, {N}, false, 1>",
+                 4: f"stage2d_em_kernel<{N}, false>"}.get(variant,
                                                                           f"stage2d_mfma_kernel<{N}, false, false>")
     out = {
         "metric": METRIC,

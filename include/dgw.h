@@ -110,8 +110,10 @@ typedef struct {
     int32_t device;      /* HIP device ordinal; -1 = host-only handle (setup only)*/
     int32_t kernel;      /* 2D stage kernel: 0 auto (FP32: 3 up to order 6, else 2;
                             FP64: 3), 1 scalar-operand VALU, 2 fused-operand
-                            MFMA, 3 derivative-first MFMA (FP32, FP64).  3D has
-                            one kernel per arithmetic (3 is DGW_EINVAL there)   */
+                            MFMA, 3 derivative-first MFMA (FP32, FP64), 4
+                            element-major MFMA (FP32; fields stored element by
+                            element, limited to 2 GiB field arrays).  3D has one
+                            kernel per arithmetic (3, 4 are DGW_EINVAL there)   */
     void *hip_stream;    /* hipStream_t to launch on; NULL = library's own stream */
 } dgw_opts;
 

@@ -161,6 +161,19 @@ __global__ void __launch_bounds__(kRedThreads) cavity_error_kernel(CavityArgs a)
     }
 }
 
+// element-major <-> tiled copy of one field array (every destination slot
+// written; pad nodes 0)
+__global__ void relayout_kernel(const float *src, float *dst, int Kp, int Np, int nf, int npp_src, int npp_dst) {
+    const int nd = npp_dst ? npp_dst : Np;
+    const size_t total = (size_t)Kp * nf * nd;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int n = int(t % nd);
+        const int f = int((t / nd) % nf);
+        const int64_t e = int64_t(t / ((size_t)nd * nf));
+        dst[fidx(e, f, n, nf, Np, npp_dst)] = n < Np ? src[fidx(e, f, n, nf, Np, npp_src)] : 0.0f;
+    }
+}
+
 // every slot of the internal array is written (padding elements and pad
 // nodes with 0)
 __global__ void to_internal_kernel(const float *src, float *dst, const int *perm, int K, int Kp, int Np, int nf,
@@ -227,6 +240,13 @@ hipError_t launch_cavity_error(const CavityArgs &a, int nblocks, hipStream_t s) 
         hipLaunchKernelGGL(cavity_error_kernel<true>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
     else
         hipLaunchKernelGGL(cavity_error_kernel<false>, dim3(nblocks), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(const float *src, float *dst, int Kp, int Np, int nf, int npp_src, int npp_dst,
+                           hipStream_t s) {
+    if (!src || !dst || src == dst) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(relayout_kernel, dim3(2048), dim3(256), 0, s, src, dst, Kp, Np, nf, npp_src, npp_dst);
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ __host__ __device__ inline size_t tix(int64_t e, int row, int rows) {
 __host__ __device__ inline size_t fidx(int64_t e, int f, int n, int nf, int Np, int npp) {
     return npp ? ((size_t)e * nf + f) * npp + n : tix(e, f * Np + n, nf * Np);
 }
-__host__ __device__ constexpr int npp3d(int Np) { return (Np + 3) / 4 * 4; }
+__host__ __device__ constexpr int npp_pad(int Np) { return (Np + 3) / 4 * 4; }
 
 // Nodes owned by lane group g (g = 0..3, lanes 16 g .. 16 g + 15) in the 3D
 // kernels: slot i = 0..kv-1 (kv = npp / 4) holds node slot_node(kv, g, i).
@@ -108,7 +108,14 @@ struct StageArgs {
 
 // Kernel variants of the fused stage (2D): fused-operand producer/consumer
 // MFMA kernel, scalar-operand VALU kernel, derivative-first MFMA kernel.
-enum StageVariant { kVariantAuto = 0, kVariantScalarOperand = 1, kVariantMfma = 2, kVariantDerivFirst = 3 };
+// Variant 4 runs on the element-major field layout (fidx with npp > 0).
+enum StageVariant {
+    kVariantAuto = 0,
+    kVariantScalarOperand = 1,
+    kVariantMfma = 2,
+    kVariantDerivFirst = 3,
+    kVariantElemMajor = 4
+};
 
 // Launch one fused stage: res <- a res + dt L(qin); qout <- qin + b res.
 hipError_t launch_stage(int dim, int N, bool material, int variant, const StageArgs &args, hipStream_t stream);
@@ -146,6 +153,19 @@ inline bool auto_deriv_first(int N) { return N <= 6; }
 // its fragment-ordered Dr, Ds, LIFT; with out == nullptr returns the length
 int opsfrag2d_df(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
 int opsfrag2d_df64(int N, const double *Dr, const double *Ds, const double *LIFT, double *out);
+
+// Element-major 2D FP32 stage (variant 4; fields in the fidx layout with
+// npp = npp_pad(Np)), persistent grid whose work-groups walk windows of
+// tiles_per_group_2d_em(N) tiles, and its operator fragments (with out ==
+// nullptr returns the number of floats)
+hipError_t launch_stage2d_em(int N, bool material, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_2d_em(int N, bool material);
+int tiles_per_group_2d_em(int N);
+int opsfrag2d_em(int N, const double *Dr, const double *Ds, const double *LIFT, float *out);
+// Copy a field array between the two field layouts (same element order):
+// src in the layout of npp_src, dst in that of npp_dst (0: tiled).
+hipError_t launch_relayout(const float *src, float *dst, int Kp, int Np, int nf, int npp_src, int npp_dst,
+                           hipStream_t stream);
 
 // Split-precision 2D stage (prec 1 = BF16 hi+lo, 2 = FP16 hi+lo), FP32
 // accumulation, FP64 geometric factors (geo64 / fgeo64).

@@ -91,14 +91,19 @@ int64_t solver_footprint(int dim, int order, int64_t K, bool material, int prec)
     const int64_t G = dim == 2 ? (material ? 6 : 4) : 9, FG = dim == 2 ? (material ? 6 : 3) : 4;
     const int64_t Kp = (K + kTile - 1) / kTile * kTile;
     const int64_t wq = prec == DGW_FP64 ? 8 : 4;        // bytes per field value
-    const int64_t npp = dim == 3 ? dgw::npp3d((int)Np) : Np;  // 3D: nodes padded to 4 per field
+    // 3D and 2D FP32 (the element-major kernel may run): nodes padded to 4 per field
+    const int64_t npp = (dim == 3 || prec == DGW_FP32) ? dgw::npp_pad((int)Np) : Np;
     int64_t b = 3 * nf * npp * Kp * wq;                  // q ping-pong and res
     b += (G + Nf * FG) * Kp * 4 + Nf * Kp * 4;          // factors and face records
     if (prec != DGW_FP32) b += (G + Nf * FG) * Kp * 8;  // FP64 factors
     const int64_t MT = (Np + 15) / 16, KV = (Np + 3) / 4, KL = (Nf * Nfp + 3) / 4;
     if (prec == DGW_FP64)  // FP64 operators, row-major and in fragment order
         b += Np * (dim * Np + Nf * Nfp) * 8 + (2 * MT * KV + MT * KL) * 64 * 8;
-    if (prec == DGW_FP32 && dim == 2) b += (2 * MT * KV + MT * KL) * 64 * 4;  // derivative-first fragments
+    if (prec == DGW_FP32 && dim == 2) {
+        const int64_t KE = dgw::npp_pad((int)Np) / 4;
+        b += (2 * MT * KV + MT * KL) * 64 * 4;                                  // derivative-first fragments
+        b += (((2 * KE + 3) / 4) * KE + ((KE + 3) / 4) * KL) * 64 * 4;          // element-major fragments
+    }
     b += Kp * 4 + Kp * 8 + dim * Np * Kp * 8;           // permutation, J, node coordinates
     if (material) b += nf * Kp * 8;                     // energy weights
     b += 4 * Np * (dim * Np + Nf * Nfp) * 4 + Np * Np * 8 + 64 * 1024;  // operators, tables, scratch
@@ -145,6 +150,7 @@ int occupancy_of(const dgw_solver *s, int variant) {
     if (s->dim == 3) return split ? dgw::blocks_per_cu_3d_split(s->N) : dgw::blocks_per_cu_3d(s->N);
     if (split) return dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec);
     if (variant == dgw::kVariantScalarOperand) return 0;
+    if (variant == dgw::kVariantElemMajor) return dgw::blocks_per_cu_2d_em(s->N, s->material);
     if (s->fp64 || variant == dgw::kVariantDerivFirst) return dgw::blocks_per_cu_2d_df(s->N, s->material, s->fp64);
     return dgw::blocks_per_cu_2d_mfma(s->N, s->material);
 }
@@ -154,8 +160,11 @@ int occupancy_of(const dgw_solver *s, int variant) {
 void set_grid(dgw_solver *s, int gpc) {
     s->gpc = gpc;
     const int ntiles = (int)(s->Kp / dgw::kTile);
+    // work units of the persistent grid: tiles, or windows of several tiles
+    const int tpu = s->dim == 2 && s->variant == dgw::kVariantElemMajor ? dgw::tiles_per_group_2d_em(s->N) : 1;
+    const int nunits = (ntiles + tpu - 1) / tpu;
     int ng = std::max(1, s->ncu) * std::max(1, gpc);
-    ng = std::min(ng, (ntiles + 7) / 8 * 8);
+    ng = std::min(ng, (nunits + 7) / 8 * 8);
     s->ngroups = std::max(8, ng / 8 * 8);
 }
 
@@ -165,7 +174,7 @@ void free_device(dgw_solver *s) {
     void *ptrs[] = {s->q[0], s->q[1], s->res, s->geo_d, s->fgeo_d, s->ops_d, s->opsfrag_d, s->nbr_d, s->itab_d, s->perm_d,
                     s->J_d, s->M_d, s->w_d, s->x_d, s->y_d, s->z_d, s->partial_d,
                     s->geo64_d, s->fgeo64_d, s->q64[0], s->q64[1], s->res64, s->ops64_d, s->opsfrag64_d,
-                    s->opsfrag_df_d};
+                    s->opsfrag_df_d, s->opsfrag_em_d};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (s->ev0) hipEventDestroy(s->ev0);
@@ -190,7 +199,7 @@ int setup_device(dgw_solver *s) {
     }
     DGW_HIP(hipEventCreate(&s->ev0));
     DGW_HIP(hipEventCreate(&s->ev1));
-    const size_t nstate = s->state_size();
+    const size_t nstate = s->state_alloc();
     int rc;
     if (s->fp64) {
         if ((rc = dalloc(&s->q64[0], nstate)) || (rc = dalloc(&s->q64[1], nstate)) || (rc = dalloc(&s->res64, nstate)))
@@ -279,7 +288,7 @@ int setup_device(dgw_solver *s) {
     std::vector<int> permv(s->perm.begin(), s->perm.end());
     const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
     const bool need64 = s->opts.prec != DGW_FP32;  // FP64 factors on the device
-    std::vector<float> opsfrag, opsfrag_df;
+    std::vector<float> opsfrag, opsfrag_df, opsfrag_em;
     std::vector<double> opsfrag64;
     if (s->fp64) {
         // FP64 fragments of the matrix-core kernel (the scalar-operand kernel
@@ -306,9 +315,12 @@ int setup_device(dgw_solver *s) {
                     return fail(DGW_EINVAL, "internal: face node order mismatch");
         opsfrag.resize(dgw::opsfrag2d(s->N, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag2d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag.data());
-        // and those of the derivative-first kernel, so that either can run
+        // and those of the derivative-first and element-major kernels, so that
+        // any of them can run
         opsfrag_df.resize(dgw::opsfrag2d_df(s->N, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag2d_df(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag_df.data());
+        opsfrag_em.resize(dgw::opsfrag2d_em(s->N, nullptr, nullptr, nullptr, nullptr));
+        dgw::opsfrag2d_em(s->N, R.Dr.a.data(), R.Ds.a.data(), R.LIFT.a.data(), opsfrag_em.data());
     } else {
         opsfrag.resize(dgw::opsfrag3d(s->N, nullptr, nullptr, nullptr, nullptr, nullptr));
         dgw::opsfrag3d(s->N, R.Dr.a.data(), R.Ds.a.data(), R.Dt.a.data(), R.LIFT.a.data(), opsfrag.data());
@@ -324,6 +336,9 @@ int setup_device(dgw_solver *s) {
     if (!opsfrag.empty() && (rc = upload(s->opsfrag_d, opsfrag))) return rc;
     if (!opsfrag_df.empty() &&
         ((rc = dalloc(&s->opsfrag_df_d, opsfrag_df.size())) || (rc = upload(s->opsfrag_df_d, opsfrag_df))))
+        return rc;
+    if (!opsfrag_em.empty() &&
+        ((rc = dalloc(&s->opsfrag_em_d, opsfrag_em.size())) || (rc = upload(s->opsfrag_em_d, opsfrag_em))))
         return rc;
     // persistent grid: every CU filled to its occupancy
     DGW_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
@@ -362,7 +377,9 @@ dgw::StageArgs stage_args(const dgw_solver *s) {
     a.fgeo64 = s->fgeo64_d;
     a.nbr = s->nbr_d;
     a.ops = s->ops_d;
-    a.opsfrag = s->dim == 2 && !s->fp64 && s->variant == dgw::kVariantDerivFirst ? s->opsfrag_df_d : s->opsfrag_d;
+    a.opsfrag = s->dim == 2 && !s->fp64 && s->variant == dgw::kVariantDerivFirst ? s->opsfrag_df_d
+                : s->dim == 2 && s->variant == dgw::kVariantElemMajor                ? s->opsfrag_em_d
+                                                                                     : s->opsfrag_d;
     a.itab = s->itab_d;
     a.Kp = (int)s->Kp;
     a.ntiles = (int)(s->Kp / dgw::kTile);
@@ -398,6 +415,7 @@ hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t 
                            : dgw::launch_stage3d_split(s->N, a, st);
     if (s->dim == 2 && s->variant == dgw::kVariantDerivFirst)
         return dgw::launch_stage2d_df(s->N, s->material, false, a, st);
+    if (s->dim == 2 && s->variant == dgw::kVariantElemMajor) return dgw::launch_stage2d_em(s->N, s->material, a, st);
     return dgw::launch_stage(s->dim, s->N, s->material, s->variant, a, st);
 }
 
@@ -552,7 +570,9 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
         return fail(DGW_EINVAL, "unknown precision variant");
     if ((opts.prec == DGW_SPLIT_FP16 || opts.prec == DGW_FP64) && mesh->dim != 2)
         return fail(DGW_EINVAL, "the 3D path has the FP32 and split-BF16 variants");
-    if (opts.kernel < 0 || opts.kernel > 3) return fail(DGW_EINVAL, "kernel variant must be 0, 1, 2 or 3");
+    if (opts.kernel < 0 || opts.kernel > 4) return fail(DGW_EINVAL, "kernel variant must be 0 .. 4");
+    if (opts.kernel == 4 && (mesh->dim != 2 || opts.prec != DGW_FP32))
+        return fail(DGW_EINVAL, "kernel 4 is the 2D FP32 element-major kernel");
     if ((opts.prec == DGW_SPLIT_BF16 || opts.prec == DGW_SPLIT_FP16) && (opts.kernel == 1 || opts.kernel == 3))
         return fail(DGW_EINVAL, "split-precision variants run on their own matrix-core kernels (kernel 0 or 2)");
     if (opts.kernel == 3 && mesh->dim != 2) return fail(DGW_EINVAL, "kernel 3 is a 2D kernel");
@@ -591,7 +611,15 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     s->nf = s->dim == 2 ? 3 : 6;
     s->K = mesh->n_elems;
     s->Kp = (s->K + dgw::kTile - 1) / dgw::kTile * dgw::kTile;
-    s->npp = s->dim == 3 ? dgw::npp3d(s->Np) : 0;
+    s->npp = (s->dim == 3 || s->variant == dgw::kVariantElemMajor) ? dgw::npp_pad(s->Np) : 0;
+    if (s->dim == 2 && !s->fp64 && (int64_t)s->state_alloc() * 4 >= (int64_t(1) << 31)) {
+        // the element-major kernel addresses partners by 32-bit byte offsets
+        if (s->variant == dgw::kVariantElemMajor) {
+            delete s;
+            return fail(DGW_ETOOBIG, "the element-major 2D kernel is limited to 2 GiB field arrays");
+        }
+        s->em_ok = false;
+    }
     if (s->dim == 3 && (int64_t)s->state_size() * 4 >= (int64_t(1) << 31)) {
         delete s;
         return fail(DGW_ETOOBIG, "3D field arrays are limited to 2 GiB (partner traces use 32-bit byte offsets)");
@@ -905,11 +933,13 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     std::vector<std::pair<int, int>> cand;  // (variant, groups per CU)
     std::vector<int> variants;
     const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
-    if (s->dim == 2 && !split)
+    if (s->dim == 2 && !split) {
         variants = s->fp64 ? std::vector<int>{dgw::kVariantDerivFirst, dgw::kVariantScalarOperand}
                            : std::vector<int>{dgw::kVariantMfma, dgw::kVariantDerivFirst, dgw::kVariantScalarOperand};
-    else
+        if (!s->fp64 && s->em_ok) variants.push_back(dgw::kVariantElemMajor);
+    } else {
         variants = {s->variant};
+    }
     for (int v : variants) {
         const int occ = occupancy_of(s, v);
         if (occ == 0)
@@ -929,7 +959,7 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
         void *p;
         ~Free() { hipFree(p); }
     } free_save{save};
-    const int cur0 = s->cur, var0 = s->variant, gpc0 = s->gpc;
+    const int cur0 = s->cur, var0 = s->variant, gpc0 = s->gpc, npp0 = s->npp;
     DGW_HIP(hipMemcpyAsync(save, cur_d, bytes, hipMemcpyDeviceToDevice, s->stream));
     DGW_HIP(hipMemcpyAsync((char *)save + bytes, res_d, bytes, hipMemcpyDeviceToDevice, s->stream));
     dgw_tune_info info{};
@@ -941,6 +971,9 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
         if (e != hipSuccess && !rc) rc = fail(DGW_EDEVICE, std::string("autotune: ") + what + ": " + hipGetErrorString(e));
         return rc == DGW_OK;
     };
+    // candidates run on the solver's buffers whatever their layout (the
+    // values only need to be finite for timing; the saved state is restored
+    // in the chosen kernel's layout at the end)
     for (size_t i = 0; i < cand.size() && rc == DGW_OK; ++i) {
         s->variant = cand[i].first;
         set_grid(s, cand[i].second);
@@ -969,19 +1002,26 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
             best_us = us;
         }
     }
-    // restore the state, keep the fastest candidate (or the old choice on error)
+    // keep the fastest candidate (or the old choice on error) and restore the
+    // state in its field layout
+    const bool ok = rc == DGW_OK && best >= 0;
+    s->variant = ok ? cand[best].first : var0;
+    s->npp = (s->dim == 3 || s->variant == dgw::kVariantElemMajor) ? dgw::npp_pad(s->Np) : 0;
+    set_grid(s, ok ? cand[best].second : gpc0);
     s->cur = cur0;
     cur_d = s->fp64 ? (void *)s->q64[s->cur] : (void *)s->q[s->cur];
-    try_hip(hipMemcpyAsync(cur_d, save, bytes, hipMemcpyDeviceToDevice, s->stream), "state restore");
-    try_hip(hipMemcpyAsync(res_d, (char *)save + bytes, bytes, hipMemcpyDeviceToDevice, s->stream), "state restore");
-    try_hip(hipStreamSynchronize(s->stream), "synchronisation");
-    if (rc || best < 0) {
-        s->variant = var0;
-        set_grid(s, gpc0);
-        return rc ? rc : fail(DGW_EINVAL, "autotune: no candidate");
+    if (s->npp == npp0) {
+        try_hip(hipMemcpyAsync(cur_d, save, bytes, hipMemcpyDeviceToDevice, s->stream), "state restore");
+        try_hip(hipMemcpyAsync(res_d, (char *)save + bytes, bytes, hipMemcpyDeviceToDevice, s->stream), "state restore");
+    } else {
+        const float *sv = static_cast<const float *>(save);
+        try_hip(dgw::launch_relayout(sv, (float *)cur_d, (int)s->Kp, s->Np, s->nf, npp0, s->npp, s->stream),
+                "state restore");
+        try_hip(dgw::launch_relayout(sv + nstate, (float *)res_d, (int)s->Kp, s->Np, s->nf, npp0, s->npp, s->stream),
+                "state restore");
     }
-    s->variant = cand[best].first;
-    set_grid(s, cand[best].second);
+    try_hip(hipStreamSynchronize(s->stream), "synchronisation");
+    if (!ok) return rc ? rc : fail(DGW_EINVAL, "autotune: no candidate");
     info.kernel = s->variant;
     info.groups_per_cu = s->gpc;
     info.best_us = best_us;

@@ -182,6 +182,7 @@ void setup(dgw_server *S, Req *r) {
         o.alpha = r->alpha;
         o.prec = r->prec;
         o.device = S->opts.device;
+        o.kernel = dgw::kVariantMfma;  // the batched launches run the fused-operand kernel on its buffers
         rc = dgw_create(&m, r->order, &o, &s);
         if (rc == DGW_OK) rc = r->q0.empty() ? dgw_set_cavity_mode(s, r->mode) : dgw_set_fields(s, r->q0.data());
         if (rc == DGW_OK) {

@@ -17,9 +17,13 @@ struct dgw_solver {
     dgw::Geometry g;
     int dim = 2, N = 1, Np = 0, Nfp = 0, Nfaces = 0, nf = 0;
     int64_t K = 0, Kp = 0;
-    int npp = 0;  // field layout (dgw::fidx): 0 = 2D tiled, 3D: padded nodes per field
-    // values in one field array (q, res)
+    int npp = 0;  // field layout (dgw::fidx): 0 = 2D tiled; 3D and the 2D element-major
+                  // kernel: padded nodes per field
+    // values in one field array (q, res) in the current layout
     size_t state_size() const { return npp ? (size_t)Kp * nf * npp : (size_t)nf * Np * Kp; }
+    // values allocated per field array: enough for either layout of a 2D FP32
+    // solve (the kernel, and with it the layout, may change by autotuning)
+    size_t state_alloc() const { return fp64 ? state_size() : (size_t)Kp * nf * ((Np + 3) / 4 * 4); }
     int G = 0, FG = 0;
     bool material = false;
     dgw_opts opts{};
@@ -32,12 +36,14 @@ struct dgw_solver {
     bool own_stream = false;
     bool fp64 = false;  // DGW_FP64: fields in q64 / res64, FP32 q / res unused
     int variant = 2;   // 2D stage kernel that runs (dgw::StageVariant, resolved)
+    bool em_ok = true; // the element-major 2D kernel may run (field arrays below 2 GiB)
     int ncu = 0, gpc = 0;  // CUs of the device, persistent work-groups per CU
     float *q[2] = {nullptr, nullptr};
     float *res = nullptr;
     double *q64[2] = {nullptr, nullptr};
     double *res64 = nullptr, *ops64_d = nullptr, *opsfrag64_d = nullptr;
     float *opsfrag_df_d = nullptr;  // FP32 2D: fragments of the derivative-first kernel
+    float *opsfrag_em_d = nullptr;  // FP32 2D: fragments of the element-major kernel
     int cur = 0;
     float *geo_d = nullptr, *fgeo_d = nullptr, *ops_d = nullptr, *opsfrag_d = nullptr;
     double *geo64_d = nullptr, *fgeo64_d = nullptr;  // split-precision and FP64 variants only

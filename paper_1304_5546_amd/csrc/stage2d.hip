@@ -264,6 +264,7 @@ hipError_t launch_stage2d_fp64(int N, bool material, const StageArgs &a, hipStre
 const char *stage_kernel_name(int dim, int N, bool material, int variant) {
     (void)N;
     if (dim == 3) return stage3d_kernel_name(N);
+    if (variant == kVariantElemMajor) return material ? "stage2d_em_kernel<N, true>" : "stage2d_em_kernel<N, false>";
     if (variant != kVariantScalarOperand) return material ? "stage2d_mfma_kernel<N, true, false>" : "stage2d_mfma_kernel<N, false, false>";
     return material ? "stage2d_kernel<float, N, true>" : "stage2d_kernel<float, N, false>";
 }

@@ -67,7 +67,7 @@ struct Tet {
     static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
     static constexpr int Nfp = (N + 1) * (N + 2) / 2;
     static constexpr int Nafp = 4 * Nfp;
-    static constexpr int NPP = npp3d(Np);        // nodes per field in memory
+    static constexpr int NPP = npp_pad(Np);        // nodes per field in memory
     static constexpr int KV = NPP / 4;           // nodes per lane group
     static constexpr int NC = KV / 4;            // 16-byte runs per lane and field
     static constexpr int NR = KV - 4 * NC;       // single nodes per lane and field
@@ -83,7 +83,10 @@ struct Tet {
     static constexpr int KT = TAIL ? TAILN / 4 : 0;                 // FP32 K steps of its tail
     static constexpr int KLS = (Nafp + 31) / 32; // K-steps of LIFT, split
     static constexpr int RS = 6 * NPP;           // floats per element
-    static constexpr int ES = RS + 4;            // LDS stride of an element's copy
+    // LDS stride of an element's copy: a multiple of 4 floats (16-byte
+    // accesses) that is 4 mod 8, so the 16 elements of a lane group fall in 8
+    // different bank quads
+    static constexpr int ES = RS % 8 == 4 ? RS : RS + 4;
     static constexpr int NT = Nafp + 4 * 6 * Nfp;
     // operator fragments: FP32 floats (derivative, then LIFT); split uint4
     // (8 BF16) hi parts (derivative, LIFT) then lo parts
@@ -172,6 +175,16 @@ __device__ __forceinline__ void face_flux(const R (&d)[6], R nx, R ny, R nz, R h
 #ifndef DGW_3D_SPD_SPLIT
 #define DGW_3D_SPD_SPLIT 1
 #endif
+// Partner traces inside the work-group's pair of tiles from the other
+// waves' LDS copies (1), or only from the wave's own copy, without
+// work-group barriers in the tile loop (0).
+#ifndef DGW_3D_SHARE
+#define DGW_3D_SHARE 1
+#endif
+// Fields of FP32 volume operands in flight ahead of their contraction.
+#ifndef DGW_3D_VPD
+#define DGW_3D_VPD 1
+#endif
 
 template <int N, bool SPLIT>
 __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
@@ -183,8 +196,9 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     __shared__ uint4 sAq[FRAG4];
     __shared__ int stab[NT];
     // split: each wave's FP64 face data of its 16 elements, [element][face * 4 + q]
-    // (n_x, n_y, n_z, Fscale), read per face node
-    __shared__ double sfd[SPLIT ? 8 : 1][16][16];
+    // (n_x, n_y, n_z, Fscale), read per face node; an element stride of 17
+    // doubles puts the 16 elements of a lane group in different banks
+    __shared__ double sfd[SPLIT ? 8 : 1][16][17];
     // each wave's copy of its 16 elements' fields, [element][field][node],
     // element stride ES
     __shared__ __attribute__((aligned(16))) float sF[8][16 * ES];
@@ -251,13 +265,16 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
 #pragma unroll
                     for (int r = 0; r < NR; ++r) b[4 * NC + r] = bload(rq, v4, (f * NPP + 16 * NC + 4 * r) * 4);
                 };
-                float bn[KV];
-                load_b(0, bn);
+                // operands of the next VPD fields in flight (a ring)
+                constexpr int VPD = DGW_3D_VPD;
+                float bn[VPD][KV];
+#pragma unroll
+                for (int f0 = 0; f0 < VPD; ++f0) load_b(f0, bn[f0]);
                 auto field = [&](auto FI) {
                     constexpr int f = decltype(FI)::value;
                     float b[KV];
 #pragma unroll
-                    for (int i = 0; i < KV; ++i) b[i] = bn[i];
+                    for (int i = 0; i < KV; ++i) b[i] = bn[f % VPD][i];
                     // the wave's LDS copy of field f
 #pragma unroll
                     for (int t = 0; t < NC; ++t)
@@ -265,7 +282,7 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                             floatx4{b[4 * t], b[4 * t + 1], b[4 * t + 2], b[4 * t + 3]};
 #pragma unroll
                     for (int r = 0; r < NR; ++r) Fc[f * NPP + 16 * NC + 4 * r + g] = b[4 * NC + r];
-                    if constexpr (f + 1 < 6) load_b(f + 1, bn);
+                    if constexpr (f + VPD < 6) load_b(f + VPD, bn[f % VPD]);
                     floatx4 d[MTD];
 #pragma unroll
                     for (int m = 0; m < MTD; ++m) d[m] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -439,7 +456,10 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
             P.wall = rc < 0;
             P.e2 = P.wall ? tile * 64 + col : (rc >> 5);
             P.pn = P.wall ? P.own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
-            P.inpair = (unsigned)((P.e2 >> 6) - 2 * pair) < 2u;
+            // with DGW_3D_SHARE = 0 a wave reads only its own LDS copy (its 16
+            // elements) and runs without work-group barriers
+            P.inpair = DGW_3D_SHARE ? (unsigned)((P.e2 >> 6) - 2 * pair) < 2u
+                                    : (P.e2 >> 4) == ((tile * 64 + col) >> 4);
             return P;
         };
         // partner traces outside the pair are gathered from memory SPD face
@@ -486,7 +506,7 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
         }
         // every wave's LDS copy of its fields is complete: partner traces of
         // elements in this pair of tiles are read from there
-        __syncthreads();
+        if (DGW_3D_SHARE) __syncthreads();
         if (active) {
             // the LIFT contraction accumulates on top of the volume part:
             // slot 4 mt + jj of lane group g = node slot i
@@ -641,7 +661,7 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                     }
             }
         }  // active
-        __syncthreads();  // the LDS copies are read by other waves until here
+        if (DGW_3D_SHARE) __syncthreads();  // the LDS copies are read by other waves until here
     }
 }
 
@@ -732,14 +752,14 @@ float bf16_value(uint16_t h) {
 // Entry of the packed derivative operator at output slot (g, s) and node
 // column n (0 outside): D_(s mod 3)[node of slot s / 3][n].
 double deriv_entry(int N, const double *const D[3], int g, int s, int n) {
-    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, KV = npp3d(Np) / 4;
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, KV = npp_pad(Np) / 4;
     if (s >= 3 * KV) return 0.0;
     const int no = slot_node(KV, g, s / 3);
     return (no < Np && n >= 0 && n < Np) ? D[s % 3][(size_t)no * Np + n] : 0.0;
 }
 // Entry of the row-permuted LIFT at output slot (g, s) and face node j.
 double lift_entry(int N, const double *LIFT, int g, int s, int j) {
-    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, KV = npp3d(Np) / 4, Nafp = 2 * (N + 1) * (N + 2);
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, KV = npp_pad(Np) / 4, Nafp = 2 * (N + 1) * (N + 2);
     if (s >= KV) return 0.0;
     const int no = slot_node(KV, g, s);
     return (no < Np && j < Nafp) ? LIFT[(size_t)no * Nafp + j] : 0.0;
@@ -754,7 +774,7 @@ double lift_entry(int N, const double *LIFT, int g, int s, int j) {
 // Returns the number of floats.
 int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, float *out) {
     const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 2 * (N + 1) * (N + 2);
-    const int KV = npp3d(Np) / 4, MTD = (3 * KV + 3) / 4, MTL = (KV + 3) / 4, KL = (Nafp + 3) / 4;
+    const int KV = npp_pad(Np) / 4, MTD = (3 * KV + 3) / 4, MTL = (KV + 3) / 4, KL = (Nafp + 3) / 4;
     const int AV = MTD * KV * 64, AL = MTL * KL * 64;
     if (!out) return AV + AL;
     const double *D[3] = {Dr, Ds, Dt};
@@ -780,7 +800,7 @@ int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const
 // 32 ks + 8 (l / 16) + q, q = 0..7 (derivative: node columns in node order;
 // LIFT: face nodes).  Returns the size in bytes (out == nullptr: size only).
 int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, void *out) {
-    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 2 * (N + 1) * (N + 2), NPP = npp3d(Np);
+    const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 2 * (N + 1) * (N + 2), NPP = npp_pad(Np);
     const int KV = NPP / 4, MTD = (3 * KV + 3) / 4, MTL = (KV + 3) / 4;
     const int TAILN = NPP % 32;
     const bool tail = NPP >= 32 && TAILN > 0 && TAILN <= 8;

@@ -142,8 +142,13 @@ def test_error_paths_before_any_device_call():
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, prec="split_fp16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec="split_fp16", kernel=1, device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, prec=7, device=-1))
-    # kernel variants: 3 is a 2D FP32/FP64 kernel, split runs its own kernels
-    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=4, device=-1))
+    # kernel variants: 3 is a 2D FP32/FP64 kernel, 4 a 2D FP32 kernel, split
+    # runs its own kernels
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=5, device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=4, prec="split_bf16", device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=4, prec="fp64", device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, kernel=4, device=-1))
+    dgw.Solver(m, 3, kernel=4, device=-1).close()
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=3, prec="split_bf16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, kernel=3, device=-1))
     # a 2D field array of 2^32 values or more (N = 8: 3 * 45 * Kp >= 2^32 from
@@ -175,7 +180,8 @@ def test_footprint_is_host_only_and_scales():
     mat = inputs.tri_grid(16, seed=1)
     mat.eps = np.full(mat.K, 2.25)
     assert dgw.footprint(mat, 5) > f5  # material factors and energy weights
-    assert dgw.footprint(m, 5, prec="split_bf16") > f5  # FP64 factors
+    # split: the state plus FP64 factors (4 + 3 x 3 values per element)
+    assert dgw.footprint(m, 5, prec="split_bf16") >= 3 * 3 * 21 * Kp * 4 + 13 * Kp * 8
     # FP64 fields: twice the state bytes, FP64 factors and operators on top
     f64 = dgw.footprint(m, 5, prec="fp64")
     assert f64 - dgw.footprint(m, 5, prec="split_bf16") > 3 * 3 * 21 * Kp * 4

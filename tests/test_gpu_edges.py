@@ -17,8 +17,8 @@ from paper_1304_5546_amd import dgw, inputs
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split_fp16": 1e-5, "fp64": 1e-12}
-KERNELS_2D = [("fp32", 1), ("fp32", 2), ("fp32", 3), ("split_bf16", 0), ("split_fp16", 0), ("fp64", 1),
-              ("fp64", 3)]
+KERNELS_2D = [("fp32", 1), ("fp32", 2), ("fp32", 3), ("fp32", 4), ("split_bf16", 0), ("split_fp16", 0),
+              ("fp64", 1), ("fp64", 3)]
 
 
 def rel(a, b):
