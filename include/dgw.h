@@ -115,6 +115,14 @@ typedef struct {
                             element, limited to 2 GiB field arrays).  3D has one
                             kernel per arithmetic (3, 4 are DGW_EINVAL there)   */
     void *hip_stream;    /* hipStream_t to launch on; NULL = library's own stream */
+    /* Work partition of the stage (section "Rethinking the Work Partition"):
+     * elements per lane of the 2D derivative-first FP32 kernel (0 or 1: one,
+     * 2: two, i.e. 32 elements per wave); wave_private = 1: in 3D each wave
+     * reads partner traces only from its own 16 elements' LDS copy and the
+     * tile loop runs without work-group barriers (0: the work-group's pair of
+     * tiles is shared through LDS).  dgw_autotune searches both. */
+    int32_t lane_elems;
+    int32_t wave_private;
 } dgw_opts;
 
 /* Fill *o with the defaults (alpha 1, cfl 1, FP32, renumber 1, device 0). */
@@ -145,6 +153,8 @@ typedef struct {
     double dof_updates_per_s; /* n_fields*K*Np*steps / solve time             */
     int32_t kernel;           /* stage kernel in use (dgw_opts.kernel numbering, resolved) */
     int32_t groups_per_cu;    /* persistent work-groups per CU (0: not persistent)     */
+    int32_t lane_elems;       /* elements per lane of the derivative-first FP32 kernel */
+    int32_t wave_private;     /* 3D work partition in use (dgw_opts.wave_private)      */
 } dgw_info;
 
 /* Set up the discretisation of order `order` on `mesh` (host FP64), upload
@@ -252,23 +262,28 @@ int dgw_launch_steps(dgw_solver *s, int64_t nsteps, double dt, void *stream);
  * work partition and keep the fastest): time `stages` fused stages (<= 0: 10, after 2 untimed ones)
  * of every candidate on this solver's own mesh and buffers, and keep the
  * fastest for all later launches.  Candidates: each 2D kernel that serves the
- * solver's arithmetic (FP32: fused-operand MFMA, derivative-first MFMA,
- * scalar-operand VALU; FP64: derivative-first MFMA, VALU; split and 3D: their
- * one kernel), each persistent kernel at 1 .. min(occupancy, 4) work-groups
- * per CU.  All candidates compute the same arithmetic per element, so results
+ * solver's arithmetic (FP32: fused-operand MFMA, derivative-first MFMA with
+ * one or two elements per lane, scalar-operand VALU, element-major MFMA;
+ * FP64: derivative-first MFMA, VALU; split: its kernel), in 3D the shared
+ * pair window and the wave-private partition, each persistent kernel at
+ * 1 .. min(occupancy, 4) work-groups per CU.  All candidates compute the same arithmetic per element, so results
  * do not depend on the choice beyond the rounding differences between
  * kernels.  The fields, the residual and the time are restored bitwise
  * afterwards.  Allocates two state-sized device buffers for the duration of
  * the call; the solver must not be in use on another thread.  out may be
  * NULL.  Errors: ENODEVICE, ENOMEM, EDEVICE. */
-#define DGW_TUNE_MAX 16
+#define DGW_TUNE_MAX 24
 typedef struct {
     int32_t kernel;          /* chosen variant (dgw_opts.kernel numbering)           */
     int32_t groups_per_cu;   /* chosen persistent work-groups per CU (0: not persistent) */
+    int32_t lane_elems;      /* chosen elements per lane (dgw_opts.lane_elems)       */
+    int32_t wave_private;    /* chosen 3D partition (dgw_opts.wave_private)          */
     double best_us;          /* its mean stage time                                  */
     int32_t n_tried;
     int32_t tried_kernel[DGW_TUNE_MAX];
     int32_t tried_groups_per_cu[DGW_TUNE_MAX];
+    int32_t tried_lane_elems[DGW_TUNE_MAX];
+    int32_t tried_wave_private[DGW_TUNE_MAX];
     double tried_us[DGW_TUNE_MAX];
 } dgw_tune_info;
 int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out);

@@ -135,7 +135,10 @@ int face_node2d(int N, int f, int t);
 int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, float *out);
 // resident work-groups per CU of the persistent 2D MFMA kernel
 int blocks_per_cu_2d_mfma(int N, bool material);
-int blocks_per_cu_3d(int N);
+// 3D: share = partner traces of the work-group's pair of tiles from the
+// other waves' LDS copies (else each wave alone, no work-group barriers)
+int blocks_per_cu_3d(int N, bool share);
+hipError_t launch_stage3d(int N, bool share, const StageArgs &a, hipStream_t s);
 
 // FP64 2D stage on FP64 fields (a.qin64 / a.qout64 / a.res64, a.geo64 /
 // a.fgeo64, a.a64 / a.b64 / a.dt64 / a.alpha64, row-major a.ops64): the
@@ -144,8 +147,9 @@ hipError_t launch_stage2d_fp64(int N, bool material, const StageArgs &a, hipStre
 // Derivative-first 2D MFMA stage, persistent grid of a.ngroups work-groups:
 // FP32 (a.qin / ..., operator fragments a.opsfrag) or FP64 (a.qin64 / ...,
 // a.opsfrag64)
-hipError_t launch_stage2d_df(int N, bool material, bool fp64, const StageArgs &a, hipStream_t s);
-int blocks_per_cu_2d_df(int N, bool material, bool fp64);
+// pairs: elements per lane, 1 or (FP32 only) 2
+hipError_t launch_stage2d_df(int N, bool material, bool fp64, int pairs, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_2d_df(int N, bool material, bool fp64, int pairs);
 // the 2D FP32 kernel that runs by default: derivative-first up to order 6,
 // fused-operand from order 7 (measured: faster at every order on 131k
 // elements, slower at order 7 on 524k)
@@ -175,8 +179,8 @@ int blocks_per_cu_2d_split(int N, bool material, int prec);
 // row-major in FP64); with out == nullptr returns the required size in bytes
 int opsfrag2d_split(int N, int prec, const double *Dr, const double *Ds, const double *LIFT, void *out);
 // Split-BF16 3D stage (FP64 geo64 / fgeo64) and its operator fragments
-hipError_t launch_stage3d_split(int N, const StageArgs &a, hipStream_t s);
-int blocks_per_cu_3d_split(int N);
+hipError_t launch_stage3d_split(int N, bool share, const StageArgs &a, hipStream_t s);
+int blocks_per_cu_3d_split(int N, bool share);
 int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, void *out);
 
 // FP64 reductions: per-block partial sums of

@@ -145,13 +145,14 @@ int upload(T *dst, const std::vector<T> &src) {
 
 // Resident work-groups per CU of the persistent kernel of `variant` on this
 // solver (0: the variant is not persistent).
-int occupancy_of(const dgw_solver *s, int variant) {
+int occupancy_of(const dgw_solver *s, int variant, int pairs, bool share) {
     const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
-    if (s->dim == 3) return split ? dgw::blocks_per_cu_3d_split(s->N) : dgw::blocks_per_cu_3d(s->N);
+    if (s->dim == 3) return split ? dgw::blocks_per_cu_3d_split(s->N, share) : dgw::blocks_per_cu_3d(s->N, share);
     if (split) return dgw::blocks_per_cu_2d_split(s->N, s->material, s->opts.prec);
     if (variant == dgw::kVariantScalarOperand) return 0;
     if (variant == dgw::kVariantElemMajor) return dgw::blocks_per_cu_2d_em(s->N, s->material);
-    if (s->fp64 || variant == dgw::kVariantDerivFirst) return dgw::blocks_per_cu_2d_df(s->N, s->material, s->fp64);
+    if (s->fp64 || variant == dgw::kVariantDerivFirst)
+        return dgw::blocks_per_cu_2d_df(s->N, s->material, s->fp64, s->fp64 ? 1 : pairs);
     return dgw::blocks_per_cu_2d_mfma(s->N, s->material);
 }
 
@@ -342,7 +343,7 @@ int setup_device(dgw_solver *s) {
         return rc;
     // persistent grid: every CU filled to its occupancy
     DGW_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->opts.device));
-    set_grid(s, occupancy_of(s, s->variant));
+    set_grid(s, occupancy_of(s, s->variant, s->pairs, s->share));
     if (dim == 3 && (rc = dalloc(&s->z_d, Z.size()))) return rc;
     if (s->material && (rc = dalloc(&s->w_d, w.size()))) return rc;
     std::vector<float> geo32(geo.begin(), geo.end()), fgeo32(fgeo.begin(), fgeo.end());
@@ -409,12 +410,13 @@ void set_stage(const dgw_solver *s, dgw::StageArgs &a, double ca, double cb, dou
 hipError_t launch_one(const dgw_solver *s, const dgw::StageArgs &a, hipStream_t st) {
     if (s->fp64)
         return s->variant == dgw::kVariantScalarOperand ? dgw::launch_stage2d_fp64(s->N, s->material, a, st)
-                                                        : dgw::launch_stage2d_df(s->N, s->material, true, a, st);
+                                                        : dgw::launch_stage2d_df(s->N, s->material, true, 1, a, st);
     if (s->opts.prec != DGW_FP32)
         return s->dim == 2 ? dgw::launch_stage2d_split(s->N, s->material, s->opts.prec, a, st)
-                           : dgw::launch_stage3d_split(s->N, a, st);
+                           : dgw::launch_stage3d_split(s->N, s->share, a, st);
     if (s->dim == 2 && s->variant == dgw::kVariantDerivFirst)
-        return dgw::launch_stage2d_df(s->N, s->material, false, a, st);
+        return dgw::launch_stage2d_df(s->N, s->material, false, s->pairs, a, st);
+    if (s->dim == 3) return dgw::launch_stage3d(s->N, s->share, a, st);
     if (s->dim == 2 && s->variant == dgw::kVariantElemMajor) return dgw::launch_stage2d_em(s->N, s->material, a, st);
     return dgw::launch_stage(s->dim, s->N, s->material, s->variant, a, st);
 }
@@ -576,6 +578,10 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
     if ((opts.prec == DGW_SPLIT_BF16 || opts.prec == DGW_SPLIT_FP16) && (opts.kernel == 1 || opts.kernel == 3))
         return fail(DGW_EINVAL, "split-precision variants run on their own matrix-core kernels (kernel 0 or 2)");
     if (opts.kernel == 3 && mesh->dim != 2) return fail(DGW_EINVAL, "kernel 3 is a 2D kernel");
+    if (opts.lane_elems < 0 || opts.lane_elems > 2) return fail(DGW_EINVAL, "lane_elems must be 0, 1 or 2");
+    if (opts.lane_elems == 2 && (mesh->dim != 2 || opts.prec != DGW_FP32 || (opts.kernel != 0 && opts.kernel != 3)))
+        return fail(DGW_EINVAL, "two elements per lane: the 2D derivative-first FP32 kernel only");
+    if (opts.wave_private != 0 && opts.wave_private != 1) return fail(DGW_EINVAL, "wave_private must be 0 or 1");
     auto t0 = std::chrono::steady_clock::now();
     dgw_solver *s = new (std::nothrow) dgw_solver();
     if (!s) return fail(DGW_ENOMEM, "host allocation failed");
@@ -589,6 +595,9 @@ int dgw_create(const dgw_mesh *mesh, int32_t order, const dgw_opts *opts_in, dgw
                      ? (s->fp64 || (plain32 && dgw::auto_deriv_first(order)) ? dgw::kVariantDerivFirst
                                                                              : dgw::kVariantMfma)
                      : (s->fp64 && opts.kernel == dgw::kVariantMfma ? dgw::kVariantDerivFirst : opts.kernel);
+    if (opts.lane_elems == 2) s->variant = dgw::kVariantDerivFirst;
+    s->pairs = opts.lane_elems == 2 ? 2 : 1;
+    s->share = opts.wave_private == 0;
     s->dim = mesh->dim;
     s->N = order;
     try {
@@ -882,6 +891,8 @@ int dgw_last_info(const dgw_solver *s, dgw_info *info) {
     *info = s->info;
     info->kernel = s->variant;
     info->groups_per_cu = s->gpc;
+    info->lane_elems = s->pairs;
+    info->wave_private = s->share ? 0 : 1;
     return DGW_OK;
 }
 
@@ -928,24 +939,38 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     if (stages <= 0) stages = 10;
     DGW_HIP(hipSetDevice(s->opts.device));
     DGW_HIP(hipStreamSynchronize(s->stream));
-    // the candidates: every stage kernel of this dimension and arithmetic, each
-    // persistent one at every work-group count per CU up to its occupancy
-    std::vector<std::pair<int, int>> cand;  // (variant, groups per CU)
-    std::vector<int> variants;
+    // the candidates: every stage kernel of this dimension and arithmetic
+    // with its work partitions (elements per lane, shared or wave-private
+    // windows), each persistent one at every work-group count per CU up to
+    // its occupancy
+    struct Cand {
+        int variant, gpc, pairs;
+        bool share;
+    };
+    std::vector<Cand> cand;
+    struct Part {
+        int variant, pairs;
+        bool share;
+    };
+    std::vector<Part> parts;
     const bool split = s->opts.prec == DGW_SPLIT_BF16 || s->opts.prec == DGW_SPLIT_FP16;
-    if (s->dim == 2 && !split) {
-        variants = s->fp64 ? std::vector<int>{dgw::kVariantDerivFirst, dgw::kVariantScalarOperand}
-                           : std::vector<int>{dgw::kVariantMfma, dgw::kVariantDerivFirst, dgw::kVariantScalarOperand};
-        if (!s->fp64 && s->em_ok) variants.push_back(dgw::kVariantElemMajor);
+    if (s->dim == 3) {
+        parts = {{s->variant, 1, true}, {s->variant, 1, false}};
+    } else if (split) {
+        parts = {{s->variant, 1, true}};
+    } else if (s->fp64) {
+        parts = {{dgw::kVariantDerivFirst, 1, true}, {dgw::kVariantScalarOperand, 1, true}};
     } else {
-        variants = {s->variant};
+        parts = {{dgw::kVariantMfma, 1, true}, {dgw::kVariantDerivFirst, 1, true}, {dgw::kVariantDerivFirst, 2, true},
+                 {dgw::kVariantScalarOperand, 1, true}};
+        if (s->em_ok) parts.push_back({dgw::kVariantElemMajor, 1, true});
     }
-    for (int v : variants) {
-        const int occ = occupancy_of(s, v);
+    for (const Part &p : parts) {
+        const int occ = occupancy_of(s, p.variant, p.pairs, p.share);
         if (occ == 0)
-            cand.push_back({v, 0});
+            cand.push_back({p.variant, 0, p.pairs, p.share});
         else
-            for (int g = 1; g <= std::min(occ, 4); ++g) cand.push_back({v, g});
+            for (int g = 1; g <= std::min(occ, 4); ++g) cand.push_back({p.variant, g, p.pairs, p.share});
     }
     if ((int)cand.size() > DGW_TUNE_MAX) cand.resize(DGW_TUNE_MAX);
     // save the state (fields, residual, ping-pong index), try every
@@ -959,7 +984,8 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
         void *p;
         ~Free() { hipFree(p); }
     } free_save{save};
-    const int cur0 = s->cur, var0 = s->variant, gpc0 = s->gpc, npp0 = s->npp;
+    const int cur0 = s->cur, var0 = s->variant, gpc0 = s->gpc, npp0 = s->npp, pairs0 = s->pairs;
+    const bool share0 = s->share;
     DGW_HIP(hipMemcpyAsync(save, cur_d, bytes, hipMemcpyDeviceToDevice, s->stream));
     DGW_HIP(hipMemcpyAsync((char *)save + bytes, res_d, bytes, hipMemcpyDeviceToDevice, s->stream));
     dgw_tune_info info{};
@@ -975,8 +1001,10 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     // values only need to be finite for timing; the saved state is restored
     // in the chosen kernel's layout at the end)
     for (size_t i = 0; i < cand.size() && rc == DGW_OK; ++i) {
-        s->variant = cand[i].first;
-        set_grid(s, cand[i].second);
+        s->variant = cand[i].variant;
+        s->pairs = cand[i].pairs;
+        s->share = cand[i].share;
+        set_grid(s, cand[i].gpc);
         dgw::StageArgs a = stage_args(s);
         auto run = [&](int n) {
             for (int k = 0; k < n && rc == DGW_OK; ++k) {
@@ -993,8 +1021,10 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
             !try_hip(hipEventElapsedTime(&ms, s->ev0, s->ev1), "event timing"))
             break;
         const double us = 1e3 * ms / stages;
-        info.tried_kernel[i] = cand[i].first;
-        info.tried_groups_per_cu[i] = cand[i].second;
+        info.tried_kernel[i] = cand[i].variant;
+        info.tried_groups_per_cu[i] = cand[i].gpc;
+        info.tried_lane_elems[i] = cand[i].pairs;
+        info.tried_wave_private[i] = cand[i].share ? 0 : 1;
         info.tried_us[i] = us;
         info.n_tried = (int)i + 1;
         if (best < 0 || us < best_us) {
@@ -1005,9 +1035,11 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     // keep the fastest candidate (or the old choice on error) and restore the
     // state in its field layout
     const bool ok = rc == DGW_OK && best >= 0;
-    s->variant = ok ? cand[best].first : var0;
+    s->variant = ok ? cand[best].variant : var0;
+    s->pairs = ok ? cand[best].pairs : pairs0;
+    s->share = ok ? cand[best].share : share0;
     s->npp = (s->dim == 3 || s->variant == dgw::kVariantElemMajor) ? dgw::npp_pad(s->Np) : 0;
-    set_grid(s, ok ? cand[best].second : gpc0);
+    set_grid(s, ok ? cand[best].gpc : gpc0);
     s->cur = cur0;
     cur_d = s->fp64 ? (void *)s->q64[s->cur] : (void *)s->q[s->cur];
     if (s->npp == npp0) {
@@ -1024,6 +1056,8 @@ int dgw_autotune(dgw_solver *s, int32_t stages, dgw_tune_info *out) {
     if (!ok) return rc ? rc : fail(DGW_EINVAL, "autotune: no candidate");
     info.kernel = s->variant;
     info.groups_per_cu = s->gpc;
+    info.lane_elems = s->pairs;
+    info.wave_private = s->share ? 0 : 1;
     info.best_us = best_us;
     if (out) *out = info;
     return DGW_OK;

@@ -37,6 +37,8 @@ struct dgw_solver {
     bool fp64 = false;  // DGW_FP64: fields in q64 / res64, FP32 q / res unused
     int variant = 2;   // 2D stage kernel that runs (dgw::StageVariant, resolved)
     bool em_ok = true; // the element-major 2D kernel may run (field arrays below 2 GiB)
+    int pairs = 1;     // elements per lane of the 2D derivative-first FP32 kernel (1 or 2)
+    bool share = true; // 3D: the work-group's pair of tiles shared through LDS
     int ncu = 0, gpc = 0;  // CUs of the device, persistent work-groups per CU
     float *q[2] = {nullptr, nullptr};
     float *res = nullptr;

@@ -218,11 +218,10 @@ static hipError_t launch2d(const StageArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_stage3d(int N, const StageArgs &args, hipStream_t stream);
 const char *stage3d_kernel_name(int N);
 
 hipError_t launch_stage(int dim, int N, bool material, int variant, const StageArgs &a, hipStream_t s) {
-    if (dim == 3) return launch_stage3d(N, a, s);
+    if (dim == 3) return launch_stage3d(N, true, a, s);
     if (variant != kVariantScalarOperand) return launch_stage2d_mfma(N, material, a, s);
 #define DGW_CASE(n)                                                    \
     case n:                                                            \

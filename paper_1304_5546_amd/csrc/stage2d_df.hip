@@ -578,16 +578,9 @@ __global__ void __launch_bounds__((64 * TriD<R, N, MAT, P>::WPB)) stage2d_df_ker
 
 namespace {
 
-// element pairs per lane in the FP32 kernel
-#ifndef DGW_DF_FP32_PAIRS
-#define DGW_DF_FP32_PAIRS 0
-#endif
-template <typename R>
-constexpr int kPairs = (sizeof(R) == 4 && DGW_DF_FP32_PAIRS) ? 2 : 1;
-
-template <typename R, int N, bool MAT>
+// P: elements per lane (1, or 2 for the FP32 kernel: element pairs)
+template <typename R, int N, bool MAT, int P>
 hipError_t launch_df(const StageArgs &a, hipStream_t s) {
-    constexpr int P = kPairs<R>;
     using X = Arith<R>;
     // every pointer the kernel dereferences must be set
     const bool bufs = X::qin(a) && X::qout(a) && X::res(a) && X::geo(a) && X::fgeo(a) && a.nbr;
@@ -598,9 +591,8 @@ hipError_t launch_df(const StageArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename R, int N, bool MAT>
+template <typename R, int N, bool MAT, int P>
 int occupancy_df() {
-    constexpr int P = kPairs<R>;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage2d_df_kernel<R, N, MAT, P>,
                                                      64 * TriD<R, N, MAT, P>::WPB, 0) != hipSuccess)
@@ -635,24 +627,27 @@ int frag_df(int N, const double *Dr, const double *Ds, const double *LIFT, R *ou
 
 #define DGW_ORDERS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
-hipError_t launch_stage2d_df(int N, bool material, bool fp64, const StageArgs &a, hipStream_t s) {
+hipError_t launch_stage2d_df(int N, bool material, bool fp64, int pairs, const StageArgs &a, hipStream_t s) {
+    if (pairs != 1 && (pairs != 2 || fp64)) return hipErrorInvalidValue;
     switch (N) {
-#define DGW_CASE(n)                                                                                        \
-    case n:                                                                                                \
-        if (fp64) return material ? launch_df<double, n, true>(a, s) : launch_df<double, n, false>(a, s); \
-        return material ? launch_df<float, n, true>(a, s) : launch_df<float, n, false>(a, s);
+#define DGW_CASE(n)                                                                                              \
+    case n:                                                                                                      \
+        if (fp64) return material ? launch_df<double, n, true, 1>(a, s) : launch_df<double, n, false, 1>(a, s); \
+        if (pairs == 2) return material ? launch_df<float, n, true, 2>(a, s) : launch_df<float, n, false, 2>(a, s); \
+        return material ? launch_df<float, n, true, 1>(a, s) : launch_df<float, n, false, 1>(a, s);
         DGW_ORDERS(DGW_CASE)
 #undef DGW_CASE
         default: return hipErrorInvalidValue;
     }
 }
 
-int blocks_per_cu_2d_df(int N, bool material, bool fp64) {
+int blocks_per_cu_2d_df(int N, bool material, bool fp64, int pairs) {
     switch (N) {
-#define DGW_CASE(n)                                                                                  \
-    case n:                                                                                          \
-        if (fp64) return material ? occupancy_df<double, n, true>() : occupancy_df<double, n, false>(); \
-        return material ? occupancy_df<float, n, true>() : occupancy_df<float, n, false>();
+#define DGW_CASE(n)                                                                                              \
+    case n:                                                                                                      \
+        if (fp64) return material ? occupancy_df<double, n, true, 1>() : occupancy_df<double, n, false, 1>();   \
+        if (pairs == 2) return material ? occupancy_df<float, n, true, 2>() : occupancy_df<float, n, false, 2>(); \
+        return material ? occupancy_df<float, n, true, 1>() : occupancy_df<float, n, false, 1>();
         DGW_ORDERS(DGW_CASE)
 #undef DGW_CASE
         default: return 1;

@@ -59,6 +59,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -81,7 +82,7 @@ struct Tet {
     static constexpr bool TAIL = NPP >= 32 && TAILN > 0 && TAILN <= 8;
     static constexpr int KVS = TAIL ? NPP / 32 : (NPP + 31) / 32;  // 16-bit K steps of a derivative
     static constexpr int KT = TAIL ? TAILN / 4 : 0;                 // FP32 K steps of its tail
-    static constexpr int KLS = (Nafp + 31) / 32; // K-steps of LIFT, split
+    static constexpr int KLS = (Nafp + 15) / 16; // K-steps of LIFT, split (16-bit products of K 16)
     static constexpr int RS = 6 * NPP;           // floats per element
     // LDS stride of an element's copy: a multiple of 4 floats (16-byte
     // accesses) that is 4 mod 8, so the 16 elements of a lane group fall in 8
@@ -91,6 +92,8 @@ struct Tet {
     // operator fragments: FP32 floats (derivative, then LIFT); split uint4
     // (8 BF16) hi parts (derivative, LIFT) then lo parts
     static constexpr int AV = MTD * KV * 64, AL = MTL * KL * 64;
+    // split: derivative fragments FV (uint4 = 8 BF16 per lane) hi then lo,
+    // LIFT fragments FL (uint2 = 4 BF16 per lane) hi then lo
     static constexpr int FV = MTD * KVS * 64, FL = MTL * KLS * 64;
     static constexpr int FT = MTD * KT * 64;  // FP32 tail fragments (floats), after the lo parts
     static_assert(16 * NC <= Np, "a 16-byte run holds no pad node");
@@ -173,26 +176,29 @@ __device__ __forceinline__ void face_flux(const R (&d)[6], R nx, R ny, R nz, R h
 #define DGW_3D_SPD 2
 #endif
 #ifndef DGW_3D_SPD_SPLIT
-#define DGW_3D_SPD_SPLIT 1
+#define DGW_3D_SPD_SPLIT 2
 #endif
-// Partner traces inside the work-group's pair of tiles from the other
-// waves' LDS copies (1), or only from the wave's own copy, without
-// work-group barriers in the tile loop (0).
-#ifndef DGW_3D_SHARE
-#define DGW_3D_SHARE 1
+// Scheduling fences of the FP32 kernel: bit 0 after each volume field, bit 1
+// after each LIFT K step (they bound the registers the compiler keeps live).
+#ifndef DGW_3D_SB
+#define DGW_3D_SB 3
 #endif
 // Fields of FP32 volume operands in flight ahead of their contraction.
 #ifndef DGW_3D_VPD
 #define DGW_3D_VPD 1
 #endif
 
-template <int N, bool SPLIT>
+// SHARE: partner traces inside the work-group's pair of tiles come from the
+// other waves' LDS copies (the work partition the library runs by default);
+// without it a wave reads only its own LDS copy and the tile loop has no
+// work-group barriers (a candidate of the automated tuning).
+template <int N, bool SPLIT, bool SHARE>
 __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     using T = Tet<N>;
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, NPP = T::NPP, KV = T::KV, NC = T::NC, NR = T::NR;
     constexpr int MTD = T::MTD, MTL = T::MTL, KL = T::KL, KVS = T::KVS, KLS = T::KLS, RS = T::RS, ES = T::ES;
     constexpr int AV = T::AV, AL = T::AL, FV = T::FV, FL = T::FL, FT = T::FT, KT = T::KT, NT = T::NT;
-    constexpr int FRAG4 = SPLIT ? 2 * (FV + FL) + (FT + 3) / 4 : (AV + AL + 3) / 4;  // in 16-byte units
+    constexpr int FRAG4 = SPLIT ? 2 * FV + FL + (FT + 3) / 4 : (AV + AL + 3) / 4;  // in 16-byte units
     __shared__ uint4 sAq[FRAG4];
     __shared__ int stab[NT];
     // split: each wave's FP64 face data of its 16 elements, [element][face * 4 + q]
@@ -311,7 +317,7 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                     for (int o = 0; o < 6; ++o)
 #pragma unroll
                         for (int i = 0; i < KV; ++i) asm volatile("" : "+v"(cv[o][i]));
-                    __builtin_amdgcn_sched_barrier(0);
+                    if (DGW_3D_SB & 1) __builtin_amdgcn_sched_barrier(0);
                 };
                 field(std::integral_constant<int, 0>{});
                 field(std::integral_constant<int, 1>{});
@@ -391,10 +397,10 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
 #pragma unroll
                         for (int m = 0; m < MTD; ++m) {
                             const int fi = (m * KVS + ks) * 64 + la;
-                            d[m] = mfma3(as_bf16x8(sAq[fi]), as_bf16x8(sAq[FV + FL + fi]), bh, bl, d[m]);
+                            d[m] = mfma3(as_bf16x8(sAq[fi]), as_bf16x8(sAq[FV + fi]), bh, bl, d[m]);
                         }
                     }
-                    const float *sT = reinterpret_cast<const float *>(sAq + 2 * (FV + FL));
+                    const float *sT = reinterpret_cast<const float *>(sAq + 2 * FV + FL);
 #pragma unroll
                     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -456,57 +462,66 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
             P.wall = rc < 0;
             P.e2 = P.wall ? tile * 64 + col : (rc >> 5);
             P.pn = P.wall ? P.own : stab[Nafp + (((rc >> 3) & 3) * 6 + (rc & 7)) * Nfp + i];
-            // with DGW_3D_SHARE = 0 a wave reads only its own LDS copy (its 16
-            // elements) and runs without work-group barriers
-            P.inpair = DGW_3D_SHARE ? (unsigned)((P.e2 >> 6) - 2 * pair) < 2u
-                                    : (P.e2 >> 4) == ((tile * 64 + col) >> 4);
+            // without SHARE only the wave's own 16 elements count
+            P.inpair = SHARE ? (unsigned)((P.e2 >> 6) - 2 * pair) < 2u : (P.e2 >> 4) == ((tile * 64 + col) >> 4);
             return P;
         };
-        // partner traces outside the pair are gathered from memory SPD face
-        // nodes ahead of their use (the first ones across the barrier below)
-        auto gather = [&](int j, float (&pb)[6]) {
-            const Partner P = partner(j);
-            if (!P.inpair) {
-                const unsigned vp = ((unsigned)P.e2 * RS + P.pn) * 4;
-#pragma unroll
-                for (int f = 0; f < 6; ++f) pb[f] = bload(rall, vp, f * NPP * 4);
-            }
-        };
-        // own and partner traces of face node j (partner from the ring
-        // slot pb when it lies outside the pair)
-        auto traces = [&](int j, const float (&pb)[6], float (&m)[6], float (&pv)[6]) {
-            const Partner P = partner(j);
-#pragma unroll
-            for (int f = 0; f < 6; ++f) m[f] = Fc[f * NPP + P.own];
+        // face node of this lane at slot t: FP32 one per K step (4 ks + g),
+        // split four per K step (16 ks + 4 g + q)
+        constexpr int NS = SPLIT ? 4 * KLS : KL;
+        constexpr int SPD = SPLIT ? DGW_3D_SPD_SPLIT : DGW_3D_SPD;
+        auto slot_j = [&](int t) { return SPLIT ? 16 * (t / 4) + 4 * g + t % 4 : 4 * t + g; };
+        // Where the traces of slot t live is worked out once, SPD slots ahead
+        // of their use (the first ones across the barrier below): the own
+        // node and the wall flag (rown), the partner's LDS offset when it lies
+        // in the pair (rloc >= 0), else its six values gathered from memory
+        // (rval)
+        float rval[SPD][6];
+        int rown[SPD], rloc[SPD];
+        const float *sFf = &sF[0][0];
+        auto gather = [&](int t, int slot) {
+            const Partner P = partner(slot_j(t));
+            rown[slot] = P.own | (P.wall ? 256 : 0);
             if (P.inpair) {
                 const int t2 = (P.e2 >> 6) - 2 * pair;
-                const float *F2 = sF[4 * t2 + ((P.e2 & 63) >> 4)] + (P.e2 & 15) * ES;
+                rloc[slot] = ((4 * t2 + ((P.e2 & 63) >> 4)) * 16 + (P.e2 & 15)) * ES + P.pn;
+            } else {
+                rloc[slot] = -1;
+                const unsigned vp = ((unsigned)P.e2 * RS + P.pn) * 4;
 #pragma unroll
-                for (int f = 0; f < 6; ++f) pv[f] = F2[f * NPP + P.pn];
+                for (int f = 0; f < 6; ++f) rval[slot][f] = bload(rall, vp, f * NPP * 4);
+            }
+        };
+        // own and partner traces of the slot's face node; returns the wall flag
+        auto traces = [&](int t, int slot, float (&m)[6], float (&pv)[6]) {
+            (void)t;
+            const int own = rown[slot] & 255, loc = rloc[slot];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) m[f] = Fc[f * NPP + own];
+            if (loc >= 0) {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) pv[f] = sFf[loc + f * NPP];
             } else {
 #pragma unroll
-                for (int f = 0; f < 6; ++f) pv[f] = pb[f];
+                for (int f = 0; f < 6; ++f) pv[f] = rval[slot][f];
             }
-            return P.wall;
+            return (rown[slot] & 256) != 0;
         };
-        // face node of this lane at slot t: FP32 one per K step (4 ks + g),
-        // split eight per K step (32 ks + 8 g + q)
-        constexpr int NS = SPLIT ? 8 * KLS : KL;
-        constexpr int SPD = SPLIT ? DGW_3D_SPD_SPLIT : DGW_3D_SPD;
-        auto slot_j = [&](int t) { return SPLIT ? 32 * (t / 8) + 8 * g + t % 8 : 4 * t + g; };
-        float ring[SPD][6];
 #pragma unroll
-        for (int t = 0; t < SPD; ++t)
+        for (int t = 0; t < SPD; ++t) {
+            rown[t] = 0;
+            rloc[t] = 0;
 #pragma unroll
-            for (int f = 0; f < 6; ++f) ring[t][f] = 0.f;
+            for (int f = 0; f < 6; ++f) rval[t][f] = 0.f;
+        }
         if (active) {
 #pragma unroll
             for (int t = 0; t < SPD; ++t)
-                if (t < NS) gather(slot_j(t), ring[t]);
+                if (t < NS) gather(t, t);
         }
         // every wave's LDS copy of its fields is complete: partner traces of
         // elements in this pair of tiles are read from there
-        if (DGW_3D_SHARE) __syncthreads();
+        if (SHARE) __syncthreads();
         if (active) {
             // the LIFT contraction accumulates on top of the volume part:
             // slot 4 mt + jj of lane group g = node slot i
@@ -529,25 +544,29 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
 #pragma unroll
                     for (int q = 0; q < 16; ++q) fd[q] = bload(rf, vcol, q * 256);
                 }
-                auto face_val = [&](int face, int q) {
-                    return face == 0 ? fd[q] : face == 1 ? fd[4 + q] : face == 2 ? fd[8 + q] : fd[12 + q];
-                };
                 const float ha = 0.5f * A.alpha;
                 // FP32 LIFT, K step ks: lane group g evaluates face node 4 ks + g
 #pragma unroll
                 for (int ks = 0; ks < KL; ++ks) {
                     const int j = 4 * ks + g;
                     float m[6], pv[6];
-                    const bool wall = traces(j, ring[ks % SPD], m, pv);
-                    if (ks + SPD < KL) gather(slot_j(ks + SPD), ring[ks % SPD]);
-                    const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
+                    const bool wall = traces(ks, ks % SPD, m, pv);
+                    if (ks + SPD < KL) gather(ks + SPD, ks % SPD);
+                    // the four face nodes of a K step lie on at most two faces,
+                    // lo and hi (fixed once the loop is unrolled): a two-way
+                    // select with constant indices
+                    constexpr int dummy = 0;
+                    const int flo = (4 * ks < Nafp ? 4 * ks : Nafp - 1) / Nfp;
+                    const int fhi = flo + 1 < 4 ? flo + 1 : 3;
+                    const bool hi = (j < Nafp ? j : Nafp - 1) >= Nfp * (flo + 1);
+                    auto fv = [&](int q) { return hi ? fd[4 * fhi + q + dummy] : fd[4 * flo + q + dummy]; };
                     float dq[6];
 #pragma unroll
                     for (int f = 0; f < 6; ++f) dq[f] = m[f] - ((wall && f >= 3) ? -pv[f] : pv[f]);
-                    const float fs = face_val(face, 3);
+                    const float fs = fv(3);
                     const float h = j < Nafp ? 0.5f * fs : 0.f, ah = j < Nafp ? ha * fs : 0.f;
                     float fl[6];
-                    face_flux<float>(dq, face_val(face, 0), face_val(face, 1), face_val(face, 2), h, ah, fl);
+                    face_flux<float>(dq, fv(0), fv(1), fv(2), h, ah, fl);
 #pragma unroll
                     for (int mt = 0; mt < MTL; ++mt) {
                         const float a = sA[AV + (mt * KL + ks) * 64 + lane];
@@ -555,7 +574,7 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                         for (int f = 0; f < 6; ++f)
                             acc[f][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, fl[f], acc[f][mt], 0, 0, 0);
                     }
-                    __builtin_amdgcn_sched_barrier(0);
+                    if (DGW_3D_SB & 2) __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
                 {
@@ -566,22 +585,23 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                 }
                 auto face_val = [&](int face, int q) { return sfd[w][c][4 * face + q]; };
                 const double ha = 0.5 * (double)A.alpha;
-                // split LIFT, K step ks: lane group g evaluates face nodes
-                // 32 ks + 8 g + q, q = 0..7
+                // split LIFT, K step ks (16 face-node rows): lane group g
+                // evaluates face nodes 16 ks + 4 g + q, q = 0..3
+                const uint2 *sL = reinterpret_cast<const uint2 *>(sAq + 2 * FV);
 #pragma unroll
                 for (int ks = 0; ks < KLS; ++ks) {
                     // hi and lo parts of the flux rows, two BF16 per word
-                    unsigned bhw[6][4], blw[6][4];
+                    unsigned bhw[6][2], blw[6][2];
 #pragma unroll
-                    for (int q2 = 0; q2 < 4; ++q2) {
+                    for (int q2 = 0; q2 < 2; ++q2) {
                         float fl2[2][6];
 #pragma unroll
                         for (int u = 0; u < 2; ++u) {
-                            const int t = 8 * ks + 2 * q2 + u;
-                            const int j = 32 * ks + 8 * g + 2 * q2 + u;
+                            const int t = 4 * ks + 2 * q2 + u;
+                            const int j = 16 * ks + 4 * g + 2 * q2 + u;
                             float m[6], pv[6];
-                            const bool wall = traces(j, ring[t % SPD], m, pv);
-                            if (t + SPD < NS) gather(slot_j(t + SPD), ring[t % SPD]);
+                            const bool wall = traces(t, t % SPD, m, pv);
+                            if (t + SPD < NS) gather(t + SPD, t % SPD);
                             const int face = (j < Nafp ? j : Nafp - 1) / Nfp;
                             double dq[6];
 #pragma unroll
@@ -606,13 +626,16 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                     }
 #pragma unroll
                     for (int mt = 0; mt < MTL; ++mt) {
-                        const int fi = FV + (mt * KLS + ks) * 64 + lane;
-                        const bf16x8 ah16 = as_bf16x8(sAq[fi]), al16 = as_bf16x8(sAq[FV + FL + fi]);
+                        const int fi = (mt * KLS + ks) * 64 + lane;
+                        const shortx4 ah16 = __builtin_bit_cast(shortx4, sL[fi]), al16 = __builtin_bit_cast(shortx4, sL[FL + fi]);
 #pragma unroll
                         for (int f = 0; f < 6; ++f) {
-                            const uint4 hu = {bhw[f][0], bhw[f][1], bhw[f][2], bhw[f][3]};
-                            const uint4 lu = {blw[f][0], blw[f][1], blw[f][2], blw[f][3]};
-                            acc[f][mt] = mfma3(ah16, al16, as_bf16x8(hu), as_bf16x8(lu), acc[f][mt]);
+                            const shortx4 bh = __builtin_bit_cast(shortx4, uint2{bhw[f][0], bhw[f][1]});
+                            const shortx4 bl = __builtin_bit_cast(shortx4, uint2{blw[f][0], blw[f][1]});
+                            floatx4 c = acc[f][mt];
+                            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah16, bh, c, 0, 0, 0);
+                            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah16, bl, c, 0, 0, 0);
+                            acc[f][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al16, bh, c, 0, 0, 0);
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);
@@ -661,71 +684,65 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                     }
             }
         }  // active
-        if (DGW_3D_SHARE) __syncthreads();  // the LDS copies are read by other waves until here
+        if (SHARE) __syncthreads();  // the LDS copies are read by other waves until here
     }
 }
 
-template <int N, bool SPLIT>
+template <int N, bool SPLIT, bool SHARE>
 static hipError_t launch3d(const StageArgs &a, hipStream_t s) {
     // every pointer the kernel dereferences must be set
     if (!a.opsfrag || !a.itab || !a.qin || !a.qout || !a.res || !a.nbr || a.ntiles <= 0 || a.ngroups < 8 ||
         (a.ngroups & 7))
         return hipErrorInvalidValue;
     if (SPLIT ? (!a.geo64 || !a.fgeo64) : (!a.geo || !a.fgeo)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage3d_kernel<N, SPLIT>), dim3(a.ngroups), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((stage3d_kernel<N, SPLIT, SHARE>), dim3(a.ngroups), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
-template <int N, bool SPLIT>
+template <int N, bool SPLIT, bool SHARE>
 static int occupancy3d() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage3d_kernel<N, SPLIT>, 512, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage3d_kernel<N, SPLIT, SHARE>, 512, 0) != hipSuccess)
+        return 1;
     return nb > 0 ? nb : 1;
 }
 
-int blocks_per_cu_3d(int N) {
+template <bool SPLIT, bool SHARE>
+static hipError_t launch3d_n(int N, const StageArgs &a, hipStream_t s) {
     switch (N) {
-        case 1: return occupancy3d<1, false>();
-        case 2: return occupancy3d<2, false>();
-        case 3: return occupancy3d<3, false>();
-        case 4: return occupancy3d<4, false>();
-        default: return 1;
-    }
-}
-
-int blocks_per_cu_3d_split(int N) {
-    switch (N) {
-        case 1: return occupancy3d<1, true>();
-        case 2: return occupancy3d<2, true>();
-        case 3: return occupancy3d<3, true>();
-        case 4: return occupancy3d<4, true>();
-        default: return 1;
-    }
-}
-
-hipError_t launch_stage3d(int N, const StageArgs &a, hipStream_t s) {
-    switch (N) {
-        case 1: return launch3d<1, false>(a, s);
-        case 2: return launch3d<2, false>(a, s);
-        case 3: return launch3d<3, false>(a, s);
-        case 4: return launch3d<4, false>(a, s);
+        case 1: return launch3d<1, SPLIT, SHARE>(a, s);
+        case 2: return launch3d<2, SPLIT, SHARE>(a, s);
+        case 3: return launch3d<3, SPLIT, SHARE>(a, s);
+        case 4: return launch3d<4, SPLIT, SHARE>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_stage3d_split(int N, const StageArgs &a, hipStream_t s) {
+template <bool SPLIT, bool SHARE>
+static int occupancy3d_n(int N) {
     switch (N) {
-        case 1: return launch3d<1, true>(a, s);
-        case 2: return launch3d<2, true>(a, s);
-        case 3: return launch3d<3, true>(a, s);
-        case 4: return launch3d<4, true>(a, s);
-        default: return hipErrorInvalidValue;
+        case 1: return occupancy3d<1, SPLIT, SHARE>();
+        case 2: return occupancy3d<2, SPLIT, SHARE>();
+        case 3: return occupancy3d<3, SPLIT, SHARE>();
+        case 4: return occupancy3d<4, SPLIT, SHARE>();
+        default: return 1;
     }
+}
+
+int blocks_per_cu_3d(int N, bool share) { return share ? occupancy3d_n<false, true>(N) : occupancy3d_n<false, false>(N); }
+int blocks_per_cu_3d_split(int N, bool share) {
+    return share ? occupancy3d_n<true, true>(N) : occupancy3d_n<true, false>(N);
+}
+hipError_t launch_stage3d(int N, bool share, const StageArgs &a, hipStream_t s) {
+    return share ? launch3d_n<false, true>(N, a, s) : launch3d_n<false, false>(N, a, s);
+}
+hipError_t launch_stage3d_split(int N, bool share, const StageArgs &a, hipStream_t s) {
+    return share ? launch3d_n<true, true>(N, a, s) : launch3d_n<true, false>(N, a, s);
 }
 
 const char *stage3d_kernel_name(int N) {
     (void)N;
-    return "stage3d_kernel<N, false>";
+    return "stage3d_kernel<N, false, true>";
 }
 
 namespace {
@@ -794,47 +811,51 @@ int opsfrag3d(int N, const double *Dr, const double *Ds, const double *Dt, const
     return AV + AL;
 }
 
-// Split operator fragments of the split 3D kernel, hi part then lo part,
-// each [derivative blocks (mt, ks)][LIFT blocks (mt, ks)] x 64 lanes x 8
-// BF16: lane l of block (mt, ks) holds row (mt, l % 16) at K rows
-// 32 ks + 8 (l / 16) + q, q = 0..7 (derivative: node columns in node order;
-// LIFT: face nodes).  Returns the size in bytes (out == nullptr: size only).
+// Split operator fragments of the split 3D kernel: the derivative blocks
+// (mt, ks) x 64 lanes x 8 BF16, hi part then lo part (lane l holds row
+// (mt, l % 16) at node columns 32 ks + 8 (l / 16) + q, q = 0..7); the LIFT
+// blocks (mt, ks) x 64 lanes x 4 BF16, hi then lo (face nodes
+// 16 ks + 4 (l / 16) + q, q = 0..3); the FP32 tail of the derivative.
+// Returns the size in bytes (out == nullptr: size only).
 int opsfrag3d_split(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, void *out) {
     const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nafp = 2 * (N + 1) * (N + 2), NPP = npp_pad(Np);
     const int KV = NPP / 4, MTD = (3 * KV + 3) / 4, MTL = (KV + 3) / 4;
     const int TAILN = NPP % 32;
     const bool tail = NPP >= 32 && TAILN > 0 && TAILN <= 8;
-    const int KVS = tail ? NPP / 32 : (NPP + 31) / 32, KT = tail ? TAILN / 4 : 0, KLS = (Nafp + 31) / 32;
+    const int KVS = tail ? NPP / 32 : (NPP + 31) / 32, KT = tail ? TAILN / 4 : 0, KLS = (Nafp + 15) / 16;
     const int FV = MTD * KVS * 64, FL = MTL * KLS * 64, FT = MTD * KT * 64;
-    const size_t total = (size_t)2 * (FV + FL) * 16 + (size_t)FT * 4;
+    const size_t total = (size_t)2 * FV * 16 + (size_t)2 * FL * 8 + (size_t)FT * 4;
     if (!out) return (int)total;
+    // 16-bit words: derivative hi [0, 8 FV), lo [8 FV, 16 FV); LIFT hi
+    // [16 FV, 16 FV + 4 FL), lo after it; then the FP32 tail
     uint16_t *o16 = static_cast<uint16_t *>(out);
-    const size_t lo_off = (size_t)(FV + FL) * 8;
-    auto put = [&](size_t frag, double v, int q) {
-        const uint16_t hi = bf16_bits((float)v);
-        const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
-        o16[frag * 8 + q] = hi;
-        o16[lo_off + frag * 8 + q] = lo;
+    auto split16 = [](double v, uint16_t &hi, uint16_t &lo) {
+        hi = bf16_bits((float)v);
+        lo = bf16_bits((float)(v - (double)bf16_value(hi)));
     };
     const double *D[3] = {Dr, Ds, Dt};
     for (int mt = 0; mt < MTD; ++mt)
         for (int ks = 0; ks < KVS; ++ks)
             for (int l = 0; l < 64; ++l) {
                 const OutSlot o = out_slot(mt, l % 16);
+                const size_t frag = (size_t)(mt * KVS + ks) * 64 + l;
                 for (int q = 0; q < 8; ++q)
-                    put((size_t)(mt * KVS + ks) * 64 + l, deriv_entry(N, D, o.g, o.s, 32 * ks + 8 * (l / 16) + q), q);
+                    split16(deriv_entry(N, D, o.g, o.s, 32 * ks + 8 * (l / 16) + q), o16[frag * 8 + q],
+                            o16[(size_t)FV * 8 + frag * 8 + q]);
             }
+    const size_t lift0 = (size_t)16 * FV;
     for (int mt = 0; mt < MTL; ++mt)
         for (int ks = 0; ks < KLS; ++ks)
             for (int l = 0; l < 64; ++l) {
                 const OutSlot o = out_slot(mt, l % 16);
-                for (int q = 0; q < 8; ++q)
-                    put((size_t)FV + (mt * KLS + ks) * 64 + l, lift_entry(N, LIFT, o.g, o.s, 32 * ks + 8 * (l / 16) + q),
-                        q);
+                const size_t frag = (size_t)(mt * KLS + ks) * 64 + l;
+                for (int q = 0; q < 4; ++q)
+                    split16(lift_entry(N, LIFT, o.g, o.s, 16 * ks + 4 * (l / 16) + q), o16[lift0 + frag * 4 + q],
+                            o16[lift0 + (size_t)FL * 4 + frag * 4 + q]);
             }
     // FP32 tail of the derivative: row (mt, l % 16), K row 4 kt + l / 16 =
     // node 32 KVS + 4 kt + l / 16
-    float *t32 = reinterpret_cast<float *>(static_cast<char *>(out) + (size_t)2 * (FV + FL) * 16);
+    float *t32 = reinterpret_cast<float *>(static_cast<char *>(out) + (size_t)2 * FV * 16 + (size_t)2 * FL * 8);
     for (int mt = 0; mt < MTD; ++mt)
         for (int kt = 0; kt < KT; ++kt)
             for (int l = 0; l < 64; ++l) {

@@ -43,22 +43,25 @@ class Mesh(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("cfl", C.c_double), ("prec", C.c_int32), ("renumber", C.c_int32),
-                ("device", C.c_int32), ("kernel", C.c_int32), ("hip_stream", C.c_void_p)]
+                ("device", C.c_int32), ("kernel", C.c_int32), ("hip_stream", C.c_void_p),
+                ("lane_elems", C.c_int32), ("wave_private", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("steps", C.c_int64), ("dt", C.c_double), ("t", C.c_double), ("setup_s", C.c_double),
                 ("solve_ms", C.c_double), ("dof_updates_per_s", C.c_double), ("kernel", C.c_int32),
-                ("groups_per_cu", C.c_int32)]
+                ("groups_per_cu", C.c_int32), ("lane_elems", C.c_int32), ("wave_private", C.c_int32)]
 
 
-TUNE_MAX = 16
+TUNE_MAX = 24
 
 
 class TuneInfo(C.Structure):
-    _fields_ = [("kernel", C.c_int32), ("groups_per_cu", C.c_int32), ("best_us", C.c_double),
+    _fields_ = [("kernel", C.c_int32), ("groups_per_cu", C.c_int32), ("lane_elems", C.c_int32),
+                ("wave_private", C.c_int32), ("best_us", C.c_double),
                 ("n_tried", C.c_int32), ("tried_kernel", C.c_int32 * TUNE_MAX),
-                ("tried_groups_per_cu", C.c_int32 * TUNE_MAX), ("tried_us", C.c_double * TUNE_MAX)]
+                ("tried_groups_per_cu", C.c_int32 * TUNE_MAX), ("tried_lane_elems", C.c_int32 * TUNE_MAX),
+                ("tried_wave_private", C.c_int32 * TUNE_MAX), ("tried_us", C.c_double * TUNE_MAX)]
 
 
 class ServerOpts(C.Structure):
@@ -188,7 +191,8 @@ class Solver:
     """One DG Maxwell solve (2D TM or 3D) on the GPU behind the C ABI."""
 
     def __init__(self, mesh, order: int, *, alpha: float = 1.0, cfl: float = 1.0, prec="fp32",
-                 renumber: bool = True, device: int = 0, stream=None, kernel: int = 0):
+                 renumber: bool = True, device: int = 0, stream=None, kernel: int = 0, lane_elems: int = 0,
+                 wave_private: int = 0):
         L = lib()
         self._keep = []
         vx = np.ascontiguousarray(mesh.vx, dtype=np.float64)
@@ -199,7 +203,8 @@ class Solver:
         mu = None if mesh.mu is None else np.ascontiguousarray(mesh.mu, dtype=np.float64)
         self._keep += [vx, vy, vz, ev, eps, mu]
         m = Mesh(mesh.dim, vx.size, _ptr(vx), _ptr(vy), _ptr(vz), ev.shape[0], _ptr(ev), _ptr(eps), _ptr(mu))
-        o = default_opts(alpha=alpha, cfl=cfl, prec=prec, renumber=int(renumber), device=device, kernel=kernel)
+        o = default_opts(alpha=alpha, cfl=cfl, prec=prec, renumber=int(renumber), device=device, kernel=kernel,
+                         lane_elems=lane_elems, wave_private=wave_private)
         if stream is not None:
             o.hip_stream = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         h = C.c_void_p()
@@ -303,8 +308,10 @@ class Solver:
         t = TuneInfo()
         _check(lib().dgw_autotune(self._h, int(stages), C.byref(t)), "dgw_autotune")
         n = t.n_tried
-        return {"kernel": t.kernel, "groups_per_cu": t.groups_per_cu, "best_us": t.best_us,
+        return {"kernel": t.kernel, "groups_per_cu": t.groups_per_cu, "lane_elems": t.lane_elems,
+                "wave_private": t.wave_private, "best_us": t.best_us,
                 "tried": [{"kernel": t.tried_kernel[i], "groups_per_cu": t.tried_groups_per_cu[i],
+                           "lane_elems": t.tried_lane_elems[i], "wave_private": t.tried_wave_private[i],
                            "us": t.tried_us[i]} for i in range(n)]}
 
     def stage_cost(self) -> tuple[float, float]:

@@ -149,6 +149,13 @@ def test_error_paths_before_any_device_call():
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=4, prec="fp64", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, kernel=4, device=-1))
     dgw.Solver(m, 3, kernel=4, device=-1).close()
+    # work partitions: two elements per lane on the derivative-first FP32 kernel only
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, lane_elems=3, device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, lane_elems=2, kernel=2, device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, lane_elems=2, prec="fp64", device=-1))
+    _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, wave_private=2, device=-1))
+    with dgw.Solver(m, 3, lane_elems=2, device=-1) as h:
+        assert h.info()["kernel"] == 3 and h.info()["lane_elems"] == 2
     _expect("DGW_EINVAL", lambda: dgw.Solver(m, 3, kernel=3, prec="split_bf16", device=-1))
     _expect("DGW_EINVAL", lambda: dgw.Solver(inputs.tet_grid(1), 2, kernel=3, device=-1))
     # a 2D field array of 2^32 values or more (N = 8: 3 * 45 * Kp >= 2^32 from

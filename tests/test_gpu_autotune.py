@@ -63,6 +63,10 @@ def _check_tuned(m, N, steps, **kw):
     kw2 = dict(kw)
     if m.dim == 2 and kw.get("prec", "fp32") in ("fp32", "fp64"):
         kw2["kernel"] = t["kernel"]
+        if t["lane_elems"] == 2:
+            kw2["lane_elems"] = 2
+    if m.dim == 3:
+        kw2["wave_private"] = t["wave_private"]
     with dgw.Solver(m, N, **kw2) as s:
         s.set_fields(before)
         s.advance_steps(steps)
@@ -76,6 +80,8 @@ def test_autotune_fp32_2d():
     t = _check_tuned(m, 5, 10)
     kernels = {c["kernel"] for c in t["tried"]}
     assert kernels == {1, 2, 3, 4}
+    # the derivative-first kernel with one and with two elements per lane
+    assert {c["lane_elems"] for c in t["tried"] if c["kernel"] == 3} == {1, 2}
     _tuned_vs_oracle(m, 5, 10)
 
 
@@ -94,4 +100,6 @@ def test_autotune_split_and_3d_vary_the_launch_shape_only():
     m3 = inputs.tet_grid(6, seed=2)
     t = _check_tuned(m3, 3, 4)
     assert len({c["kernel"] for c in t["tried"]}) == 1
+    # the shared pair window and the wave-private partition
+    assert {c["wave_private"] for c in t["tried"]} == {0, 1}
     _tuned_vs_oracle(m3, 3, 4)

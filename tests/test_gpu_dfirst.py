@@ -37,18 +37,22 @@ def _mesh(s, seed, permute, mat):
     return m
 
 
+@pytest.mark.parametrize("lane_elems", [1, 2])
 @pytest.mark.parametrize("s,N,seed,permute,mat,alpha", CASES)
-def test_dfirst_rhs_parity(s, N, seed, permute, mat, alpha):
+def test_dfirst_rhs_parity(s, N, seed, permute, mat, alpha, lane_elems):
+    """One and two elements per lane (the work partitions dgw_autotune
+    searches) against the oracle."""
     m = _mesh(s, seed, permute, mat)
     d = oracle.Discretization2D(m.vx, m.vy, m.elem_verts, N, eps=m.eps, mu=m.mu)
     op = oracle.Maxwell2D(d, alpha)
-    with dgw.Solver(m, N, alpha=alpha, kernel=3) as sol:
+    with dgw.Solver(m, N, alpha=alpha, kernel=3, lane_elems=lane_elems) as sol:
+        assert sol.info()["lane_elems"] == lane_elems
         rng = np.random.default_rng(seed)
         q = rng.standard_normal(sol.shape)
         err = rel(sol.rhs(q), op.rhs(q))
         qs = oracle.cavity_mode_2d(d.x, d.y, 0.3, 2, 1)
         err2 = rel(sol.rhs(qs), op.rhs(qs))
-    print(f"kernel 3 rhs s={s} N={N} K={m.K}: random {err:.2e}, smooth {err2:.2e}")
+    print(f"kernel 3 x{lane_elems} rhs s={s} N={N} K={m.K}: random {err:.2e}, smooth {err2:.2e}")
     assert err < 1e-5
     assert err2 < 1e-5
 
