@@ -94,6 +94,12 @@ __device__ __forceinline__ TileSrc tile_src(const StageArgs &A, int t) {
 
 }  // namespace
 
+// Consumer K-steps between scheduling fences (0: none): the fences keep the
+// operand reads of later K-steps from being hoisted into long-lived registers.
+#ifndef DGW_MF_SB
+#define DGW_MF_SB 2
+#endif
+
 template <int N, bool MAT, bool BATCH>
 __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     using T = Tri<N, MAT>;
@@ -294,7 +300,7 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                 }
                 // keep the operand reads of later K-steps from being hoisted
                 // into long-lived registers
-                if (ks % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                if (DGW_MF_SB > 0 && ks % DGW_MF_SB == DGW_MF_SB - 1) __builtin_amdgcn_sched_barrier(0);
             }
 
             // upwind flux of this wave's 16 elements (lane group g takes face
@@ -364,7 +370,7 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                 }
                 // keep the operand reads of later K-steps from being hoisted
                 // into long-lived registers
-                if (ks % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                if (DGW_MF_SB > 0 && ks % DGW_MF_SB == DGW_MF_SB - 1) __builtin_amdgcn_sched_barrier(0);
             }
 
             // fused low-storage RK update (lane holds rows 16mt+4g+jj of column col)
