@@ -281,16 +281,18 @@ def main():
     launch_s = ms * 1e-3 / (5 * args.steps)
     achieved = bytes_per_launch / launch_s / 1e9
     pcode = {"fp32": 0, "split_bf16": 1, "split_fp16": 2, "fp64": 3}[args.prec]
-    variant = solver.info()["kernel"]
+    sinfo = solver.info()
+    variant = sinfo["kernel"]
     if dim == 3:
-        kname = f"stage3d_kernel<{N}, {'true' if pcode else 'false'}>"
+        kname = (f"stage3d_kernel<{N}, {'true' if pcode else 'false'}, "
+                 f"{'false' if sinfo['wave_private'] else 'true'}>")
     elif pcode == 3:
         kname = f"stage2d_kernel<double, {N}, false>" if variant == 1 else f"stage2d_df_kernel<double, {N}, false, 1>"
     elif pcode:
         kname = f"stage2d_split_kernel<{N}, false, {pcode}>"
     else:
         kname = {1: f"stage2d_kernel<float, {N}, false>",
-                 3: f"stage2d_df_kernel<float, {N}, false, 1>",
+                 3: f"stage2d_df_kernel<float, {N}, false, {2 if sinfo['lane_elems'] == 2 else 1}>",
                  4: f"stage2d_em_kernel<{N}, false>"}.get(variant,
                                                                           f"stage2d_mfma_kernel<{N}, false, false>")
     out = {

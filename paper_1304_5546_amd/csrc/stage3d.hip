@@ -178,6 +178,19 @@ __device__ __forceinline__ void face_flux(const R (&d)[6], R nx, R ny, R nz, R h
 #ifndef DGW_3D_SPD_SPLIT
 #define DGW_3D_SPD_SPLIT 2
 #endif
+// FP32: the next work unit's factors and first operands loaded before this
+// unit's update (1) or at the next unit's start (0).
+#ifndef DGW_3D_NPF
+#define DGW_3D_NPF 0
+#endif
+// Fields whose residual runs are loaded before the surface loop (the rest at
+// the update).
+#ifndef DGW_3D_RPF
+#define DGW_3D_RPF 6
+#endif
+#ifndef DGW_3D_RPF_SPLIT
+#define DGW_3D_RPF_SPLIT 0
+#endif
 // Scheduling fences of the FP32 kernel: bit 0 after each volume field, bit 1
 // after each LIFT K step (they bound the registers the compiler keeps live).
 #ifndef DGW_3D_SB
@@ -230,6 +243,10 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     const int xbase = x * q8 + (x < r8 ? x : r8), xcount = q8 + (x < r8 ? 1 : 0);
 
     float *F = sF[w];
+    // FP32 with DGW_3D_NPF: the next work unit's factors and first field's
+    // operands, loaded during this unit's surface phase
+    float nG[9], nb0[Tet<N>::KV];
+    bool npf_ok = false;
     for (int pl = bi; pl < xcount; pl += GB) {
         const int pair = xbase + pl;
         const int tile = 2 * pair + (w >> 2);
@@ -260,7 +277,10 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                 // (K row 4 ks + g = node slot ks); the next field's are in
                 // flight while field f is contracted
                 float G[9];
-                {
+                if (DGW_3D_NPF && npf_ok) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) G[q] = nG[q];
+                } else {
                     const __amdgpu_buffer_rsrc_t rg = rsrc(A.geo + (size_t)tile * (9 * 64), 9 * 64 * 4);
 #pragma unroll
                     for (int q = 0; q < 9; ++q) G[q] = bload(rg, vcol, q * 256);
@@ -275,7 +295,14 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                 constexpr int VPD = DGW_3D_VPD;
                 float bn[VPD][KV];
 #pragma unroll
-                for (int f0 = 0; f0 < VPD; ++f0) load_b(f0, bn[f0]);
+                for (int f0 = 0; f0 < VPD; ++f0) {
+                    if (f0 == 0 && DGW_3D_NPF && npf_ok) {
+#pragma unroll
+                        for (int i = 0; i < KV; ++i) bn[0][i] = nb0[i];
+                    } else {
+                        load_b(f0, bn[f0]);
+                    }
+                }
                 auto field = [&](auto FI) {
                     constexpr int f = decltype(FI)::value;
                     float b[KV];
@@ -523,6 +550,21 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
         // elements in this pair of tiles are read from there
         if (SHARE) __syncthreads();
         if (active) {
+            // residual runs of the first RPF fields: loaded here, used in the
+            // update after the surface loop (their latency hides behind it)
+            const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (64 * RS), TB);
+            const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (64 * RS), TB);
+            constexpr int RPF = SPLIT ? DGW_3D_RPF_SPLIT : DGW_3D_RPF;
+            float rv[6][KV];
+            auto load_res = [&](int f) {
+#pragma unroll
+                for (int t = 0; t < NC; ++t) bload4(rr, v16, (f * NPP + 16 * t) * 4, &rv[f][4 * t]);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) rv[f][4 * NC + r] = bload(rr, v4, (f * NPP + 16 * NC + 4 * r) * 4);
+            };
+#pragma unroll
+            for (int f = 0; f < RPF; ++f) load_res(f);
+            if (RPF > 0) __builtin_amdgcn_sched_barrier(0);  // issued here, not sunk to the update
             // the LIFT contraction accumulates on top of the volume part:
             // slot 4 mt + jj of lane group g = node slot i
             floatx4 acc[6][MTL];
@@ -642,19 +684,27 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                 }
             }
 
-            // ---- fused low-storage RK update of the lane's nodes: every
-            // residual load first (their latencies overlap), then per field
-            // the arithmetic and the stores
-            const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (64 * RS), TB);
-            const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (64 * RS), TB);
-            float rv[6][KV];
+            // the next unit's factors and first operands (FP32, DGW_3D_NPF)
+            if constexpr (!SPLIT && DGW_3D_NPF) {
+                const int pl2 = pl + GB, tile2 = 2 * (xbase + pl2) + (w >> 2);
+                npf_ok = pl2 < xcount && tile2 < A.ntiles;  // wave-uniform
+                if (npf_ok) {
+                    const __amdgpu_buffer_rsrc_t rg2 = rsrc(A.geo + (size_t)tile2 * (9 * 64), 9 * 64 * 4);
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
+                    for (int q = 0; q < 9; ++q) nG[q] = bload(rg2, vcol, q * 256);
+                    const __amdgpu_buffer_rsrc_t rq2 = rsrc(A.qin + (size_t)tile2 * (64 * RS), TB);
 #pragma unroll
-                for (int t = 0; t < NC; ++t) bload4(rr, v16, (f * NPP + 16 * t) * 4, &rv[f][4 * t]);
+                    for (int t = 0; t < NC; ++t) bload4(rq2, v16, (16 * t) * 4, &nb0[4 * t]);
 #pragma unroll
-                for (int r = 0; r < NR; ++r) rv[f][4 * NC + r] = bload(rr, v4, (f * NPP + 16 * NC + 4 * r) * 4);
+                    for (int r = 0; r < NR; ++r) nb0[4 * NC + r] = bload(rq2, v4, (16 * NC + 4 * r) * 4);
+                }
             }
+            // ---- fused low-storage RK update of the lane's nodes: every
+            // residual load first (their latencies overlap; the first RPF
+            // fields' were issued before the surface loop), then per field
+            // the arithmetic and the stores
+#pragma unroll
+            for (int f = RPF; f < 6; ++f) load_res(f);
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
                 float qv[KV];
