@@ -58,7 +58,6 @@ struct Tri {
     // accesses free of bank conflicts
     static constexpr int SUB = R * 16 + ((R & 1) ? 0 : 16);
     static constexpr int BUF = 4 * SUB;
-    static constexpr int PW = (RP + 3) / 4;      // plain rows per producer wave
     static constexpr int JW = (Nafp + 3) / 4;    // face nodes per producer wave
     // index of lattice node (i, j) in the order "for j, for i in 0..N-j"
     __host__ __device__ static constexpr int lat(int i, int j) { return j * (N + 1) - j * (j - 1) / 2 + i; }
@@ -100,12 +99,23 @@ __device__ __forceinline__ TileSrc tile_src(const StageArgs &A, int t) {
 #define DGW_MF_SB 2
 #endif
 
+// Highest order whose consumers load the residual rows of their next tile at
+// the end of the current one.
+#ifndef DGW_MF_XRES_MAX
+#define DGW_MF_XRES_MAX 6
+#endif
+// Producer pause (units of 64 cycles) at the top of each tile, so that the
+// consumers' residual loads are issued ahead of the producers' stream.
+#ifndef DGW_MF_PSLEEP
+#define DGW_MF_PSLEEP 0
+#endif
+
 template <int N, bool MAT, bool BATCH>
 __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     using T = Tri<N, MAT>;
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, Kd = T::Kd, KS = T::KS, MT = T::MT, KV = T::KV;
     constexpr int G = T::G, FG = T::FG, RG = T::RG, RF = T::RF, RP = T::RP, SUB = T::SUB, BUF = T::BUF;
-    constexpr int PW = T::PW, JW = T::JW;
+    constexpr int JW = T::JW;
     __shared__ float sbuf[2 * BUF];
     __shared__ float sa[MT * KS * 64];
 
@@ -149,19 +159,20 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
         // live (and occupy registers) in the other role's code as well
         int ln = lane;
         asm volatile("" : "+v"(ln));
-        float pl[PW];
+        // plain rows (fields, factors, face data) in quads of 4 rows x 64
+        // elements, one 16-byte access per lane: lane l takes row
+        // 4 quad + l/16, elements 4 (l%16) .. 4 (l%16) + 3; producer w
+        // takes quads w, w + 4, ...
+        constexpr int PV = ((RP + 3) / 4 + 3) / 4;
+        floatx4 pv[PV];
+        const int lr = ln >> 4, le = 4 * (ln & 15);
 #pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            const int r = w + 4 * i;
-            float v = 0.f;
-            if (r < RG)
-                v = qt[(unsigned)(r * 64 + ln)];
-            else if (r < RF)
-                v = gt[(unsigned)((r - RG) * 64 + ln)];
-            else if (r < RP)
-                v = ft[(unsigned)((r - RF) * 64 + ln)];
-            pl[i] = v;
+        for (int i = 0; i < PV; ++i) {
+            const int r = 4 * (w + 4 * i) + lr;
+            const float *src = r < RG ? qt + r * 64 : (r < RF ? gt + (r - RG) * 64 : ft + (r - RF) * 64);
+            pv[i] = r < RP ? *reinterpret_cast<const floatx4 *>(src + le) : floatx4{0.f, 0.f, 0.f, 0.f};
         }
+        // partner traces of the face nodes j = w + 4 i
         float pt[JW][3];
 #pragma unroll
         for (int i = 0; i < JW; ++i) {
@@ -181,10 +192,12 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
             }
         }
         float *B = sbuf + b * BUF + prow;
+        // element 4 (l%16) + q of a quad row lies in sub-tile (l%16)/4, column 4 (l%4) + q
+        float *Bv = sbuf + b * BUF + ((ln & 15) >> 2) * SUB + 4 * (ln & 3);
 #pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            const int r = w + 4 * i;
-            if (r < RP) B[r * 16] = pl[i];
+        for (int i = 0; i < PV; ++i) {
+            const int r = 4 * (w + 4 * i) + lr;
+            if (r < RP) *reinterpret_cast<floatx4 *>(Bv + r * 16) = pv[i];
         }
 #pragma unroll
         for (int i = 0; i < JW; ++i) {
@@ -203,28 +216,30 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     }
     __syncthreads();
 
-    // consumers: the residual rows of their next tile are loaded at the end of
-    // the current one (they stay in flight across the barrier).  Up to N = 6
-    // this also frees enough registers for two resident work-groups per CU;
-    // at N = 7, 8 (one work-group either way) they are loaded at tile start
-    constexpr bool XRES = N <= 6;
-    float rrn[XRES ? 3 : 1][MT][4];
+    // Consumer memory traffic is row-major and 16 bytes wide: lane l covers
+    // field rows 16 rg + l/4 and, of the wave's 16 elements, the four columns
+    // 4 (l%4) .. 4 (l%4) + 3 (one 64-byte run per row).  The residual rows are
+    // loaded so; at the end of the tile the right-hand side is transposed to
+    // that order through the wave's own LDS sub-tile.  One 16-byte access per
+    // row group instead of one 4-byte access per row and lane group keeps
+    // the consumers' vector-memory instructions (which queue behind the
+    // producers' stream) to 3 RGN per tile.
+    constexpr int RGN = (3 * Np + 15) / 16;
+    // the residual rows of the next tile are loaded at the end of the current
+    // one (in flight across the barrier) up to order DGW_MF_XRES_MAX, else at
+    // tile start
+    constexpr bool XRES = N <= DGW_MF_XRES_MAX;
+    floatx4 rrn[RGN];
     auto load_res = [&](int tile) {
         const TileSrc S = tile_src<BATCH>(A, tile);
         int ln = lane;
         asm volatile("" : "+v"(ln));
-        const int cl = 16 * w + (ln & 15), gl = ln >> 4;
-        const float *rt = S.res + (size_t)S.tile * (3 * Np * 64);
-        if constexpr (XRES) {
+        const float *rt = S.res + (size_t)S.tile * (3 * Np * 64) + 16 * w + 4 * (ln & 3);
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) {
-                        const int n = 16 * mt + 4 * gl + jj;
-                        rrn[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + cl)] : 0.f;
-                    }
+        for (int rg = 0; rg < RGN; ++rg) {
+            const int row = 16 * rg + (ln >> 2);
+            rrn[rg] = row < 3 * Np ? *reinterpret_cast<const floatx4 *>(rt + (unsigned)(row * 64))
+                                   : floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
     if (XRES && !producer) load_res(xbase + bi);
@@ -234,14 +249,13 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
         const int cur = it & 1;
         if (producer) {
             const int tn = tl + GB;
+            if (DGW_MF_PSLEEP > 0) __builtin_amdgcn_s_sleep(DGW_MF_PSLEEP);
             if (tn < xcount) {
                 produce(xbase + tn, cur ^ 1);
                 if (tn + GB < xcount) load_recs(xbase + tn + GB);
             }
         } else {
             const int tile = xbase + tl;
-            int col = 16 * w + c;
-            asm volatile("" : "+v"(col));  // see the producer's note
             const TileSrc S = tile_src<BATCH>(A, tile);
             float *rt = S.res + (size_t)S.tile * (3 * Np * 64);
             float *ot = S.qout + (size_t)S.tile * (3 * Np * 64);
@@ -249,20 +263,10 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
             const float *B = sbuf + cur * BUF + w * SUB + c;  // this wave's sub-tile, column c
             float *Bw = sbuf + cur * BUF + w * SUB + c;
 
-            float rr[3][MT][4];
+            if (!XRES) load_res(tile);
+            floatx4 rr[RGN];
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) {
-                        if constexpr (XRES) {
-                            rr[f][mt][jj] = rrn[f][mt][jj];
-                        } else {
-                            const int n = 16 * mt + 4 * g + jj;
-                            rr[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
-                        }
-                    }
+            for (int rg = 0; rg < RGN; ++rg) rr[rg] = rrn[rg];
 
             const float rx = B[(RG + 0) * 16], ry = B[(RG + 1) * 16];
             const float sx = B[(RG + 2) * 16], sy = B[(RG + 3) * 16];
@@ -373,7 +377,19 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                 if (DGW_MF_SB > 0 && ks % DGW_MF_SB == DGW_MF_SB - 1) __builtin_amdgcn_sched_barrier(0);
             }
 
-            // fused low-storage RK update (lane holds rows 16mt+4g+jj of column col)
+            // fused low-storage RK update, row-major.  The lane's q_in rows are
+            // read first; the right-hand side (rows 16mt+4g+jj of column c in
+            // the accumulators) is then written over the sub-tile's field rows
+            // and read back in the row-major order (LDS operations of one wave
+            // complete in order).
+            float *Bs = Bw - c;
+            const int lr = lane >> 2, lc = 4 * (lane & 3);
+            floatx4 qv[RGN];
+#pragma unroll
+            for (int rg = 0; rg < RGN; ++rg) {
+                const int row = 16 * rg + lr;
+                qv[rg] = row < 3 * Np ? *reinterpret_cast<const floatx4 *>(Bs + row * 16 + lc) : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -381,13 +397,24 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int n = 16 * mt + 4 * g + jj;
-                        if (n < Np) {
-                            const unsigned idx = (unsigned)((f * Np + n) * 64 + col);
-                            const float r = A.a * rr[f][mt][jj] + dt * acc[f][mt][jj];
-                            rt[idx] = r;
-                            ot[idx] = B[(f * Np + n) * 16] + A.b * r;
-                        }
+                        if (n < Np) Bw[(f * Np + n) * 16] = acc[f][mt][jj];
                     }
+            float *rtl = rt + 16 * w + lc, *otl = ot + 16 * w + lc;
+#pragma unroll
+            for (int rg = 0; rg < RGN; ++rg) {
+                const int row = 16 * rg + lr;
+                if (row < 3 * Np) {
+                    const floatx4 rh = *reinterpret_cast<const floatx4 *>(Bs + row * 16 + lc);
+                    floatx4 r, qo;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        r[q] = A.a * rr[rg][q] + dt * rh[q];
+                        qo[q] = qv[rg][q] + A.b * r[q];
+                    }
+                    *reinterpret_cast<floatx4 *>(rtl + (unsigned)(row * 64)) = r;
+                    *reinterpret_cast<floatx4 *>(otl + (unsigned)(row * 64)) = qo;
+                }
+            }
             if (XRES && tl + GB < xcount) load_res(xbase + tl + GB);
         }
         __syncthreads();

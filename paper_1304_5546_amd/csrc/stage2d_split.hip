@@ -62,7 +62,6 @@ struct TriS {
     static constexpr int R = RP + 3 * Nafp;
     static constexpr int SUB = R * 16 + ((R & 1) ? 0 : 16);
     static constexpr int BUF = 4 * SUB;
-    static constexpr int QW = (RP + 3) / 4;
     static constexpr int JW = (Nafp + 3) / 4;
     __host__ __device__ static constexpr int lat(int i, int j) { return j * (N + 1) - j * (j - 1) / 2 + i; }
     __host__ __device__ static constexpr int face_node(int f, int t) {
@@ -98,6 +97,12 @@ __device__ __forceinline__ void pow2_scale(float mx, float &scale, float &unscal
 
 }  // namespace
 
+// Producer pause (units of 64 cycles) at the top of each tile, so that the
+// consumers' loads are issued ahead of the producers' stream.
+#ifndef DGW_SP_PSLEEP
+#define DGW_SP_PSLEEP 0
+#endif
+
 template <int N, bool MAT, int PREC>
 __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
     using T = TriS<N, MAT>;
@@ -106,7 +111,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
     typedef typename H::V hv;
     constexpr int Np = T::Np, Nfp = T::Nfp, Nafp = T::Nafp, KV = T::KV, KF = T::KF, MT = T::MT;
     constexpr int FV = T::FV, FA = T::FA;
-    constexpr int G = T::G, FG = T::FG, RP = T::RP, SUB = T::SUB, BUF = T::BUF, QW = T::QW, JW = T::JW;
+    constexpr int G = T::G, FG = T::FG, RP = T::RP, SUB = T::SUB, BUF = T::BUF, JW = T::JW;
     __shared__ float sbuf[2 * BUF];
     __shared__ uint4 sa[2 * FA];  // operator fragments: hi parts, then lo parts
 
@@ -139,11 +144,16 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
         int rec[3] = {rec_next[0], rec_next[1], rec_next[2]};
         int ln = lane0;
         asm volatile("" : "+v"(ln));
-        float pl[QW];
+        // field rows in quads of 4 rows x 64 elements, one 16-byte access per
+        // lane: lane l takes row 4 quad + l/16, elements 4 (l%16) .. + 3;
+        // producer w takes quads w, w + 4, ...
+        constexpr int PV = ((RP + 3) / 4 + 3) / 4;
+        floatx4 pv[PV];
+        const int lr = ln >> 4, le = 4 * (ln & 15);
 #pragma unroll
-        for (int i = 0; i < QW; ++i) {
-            const int r = w + 4 * i;
-            pl[i] = r < RP ? qt[(unsigned)(r * 64 + ln)] : 0.f;
+        for (int i = 0; i < PV; ++i) {
+            const int r = 4 * (w + 4 * i) + lr;
+            pv[i] = r < RP ? *reinterpret_cast<const floatx4 *>(qt + (unsigned)(r * 64 + le)) : floatx4{0.f, 0.f, 0.f, 0.f};
         }
         float pt[JW][3];
 #pragma unroll
@@ -163,10 +173,12 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             }
         }
         float *Bp = sbuf + b * BUF + prow;
+        // element 4 (l%16) + q of a quad row lies in sub-tile (l%16)/4, column 4 (l%4) + q
+        float *Bv = sbuf + b * BUF + ((ln & 15) >> 2) * SUB + 4 * (ln & 3);
 #pragma unroll
-        for (int i = 0; i < QW; ++i) {
-            const int r = w + 4 * i;
-            if (r < RP) Bp[r * 16] = pl[i];
+        for (int i = 0; i < PV; ++i) {
+            const int r = 4 * (w + 4 * i) + lr;
+            if (r < RP) *reinterpret_cast<floatx4 *>(Bv + r * 16) = pv[i];
         }
 #pragma unroll
         for (int i = 0; i < JW; ++i) {
@@ -186,22 +198,23 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
     __syncthreads();
 
     // consumers: the residual rows of their next tile are loaded at the end of
-    // the current one, so the update never waits on memory
-    float rrn[3][MT][4];
+    // the current one, so the update never waits on memory.  Consumer memory
+    // traffic is row-major and 16 bytes wide: lane l covers field rows
+    // 16 rg + l/4 and, of the wave's 16 elements, the columns 4 (l%4) .. + 3;
+    // the right-hand side is transposed to that order through the wave's own
+    // LDS sub-tile at the update (3 RGN vector-memory instructions per tile)
+    constexpr int RGN = (3 * Np + 15) / 16;
+    floatx4 rrn[RGN];
     auto load_res = [&](int tile) {
         int ln = lane0;
         asm volatile("" : "+v"(ln));
-        const int col = 16 * w + (ln & 15), g = ln >> 4;
-        const float *rt = A.res + (size_t)tile * (3 * Np * 64);
+        const float *rt = A.res + (size_t)tile * (3 * Np * 64) + 16 * w + 4 * (ln & 3);
 #pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int n = 16 * mt + 4 * g + jj;
-                    rrn[f][mt][jj] = n < Np ? rt[(unsigned)((f * Np + n) * 64 + col)] : 0.f;
-                }
+        for (int rg = 0; rg < RGN; ++rg) {
+            const int row = 16 * rg + (ln >> 2);
+            rrn[rg] = row < 3 * Np ? *reinterpret_cast<const floatx4 *>(rt + (unsigned)(row * 64))
+                                   : floatx4{0.f, 0.f, 0.f, 0.f};
+        }
     };
     if (!producer) load_res(xbase + bi);
 
@@ -210,6 +223,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
         const int cur = it & 1;
         if (producer) {
             const int tn = tl + GB;
+            if (DGW_SP_PSLEEP > 0) __builtin_amdgcn_s_sleep(DGW_SP_PSLEEP);
             if (tn < xcount) {
                 produce(xbase + tn, cur ^ 1);
                 if (tn + GB < xcount) load_recs(xbase + tn + GB);
@@ -224,13 +238,9 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             float *rt = A.res + (size_t)tile * (3 * Np * 64);
             float *ot = A.qout + (size_t)tile * (3 * Np * 64);
 
-            float rr[3][MT][4];
+            floatx4 rr[RGN];
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) rr[f][mt][jj] = rrn[f][mt][jj];
+            for (int rg = 0; rg < RGN; ++rg) rr[rg] = rrn[rg];
             // FP64 geometric factors and face data of column col
             const double *gt = A.geo64 + (size_t)tile * (G * 64);
             const double rx = gt[0 * 64 + col], ry = gt[1 * 64 + col], sx = gt[2 * 64 + col], sy = gt[3 * 64 + col];
@@ -400,7 +410,18 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     for (int jj = 0; jj < 4; ++jj) acc[f][mt][jj] = cv[f][mt][jj] + t[mt][jj] * unscale;
             }
 
-            // fused low-storage RK update
+            // fused low-storage RK update, row-major: the lane's q_in rows are
+            // read first, the right-hand side (rows 16mt+4g+jj of column c) is
+            // written over the sub-tile's field rows and read back row-major
+            // (LDS operations of one wave complete in order)
+            float *Bs = B - c;
+            const int lr = lane >> 2, lc = 4 * (lane & 3);
+            floatx4 qv[RGN];
+#pragma unroll
+            for (int rg = 0; rg < RGN; ++rg) {
+                const int row = 16 * rg + lr;
+                qv[rg] = row < 3 * Np ? *reinterpret_cast<const floatx4 *>(Bs + row * 16 + lc) : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -408,13 +429,24 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int n = 16 * mt + 4 * g + jj;
-                        if (n < Np) {
-                            const unsigned idx = (unsigned)((f * Np + n) * 64 + col);
-                            const float r = A.a * rr[f][mt][jj] + A.dt * acc[f][mt][jj];
-                            rt[idx] = r;
-                            ot[idx] = B[(f * Np + n) * 16] + A.b * r;
-                        }
+                        if (n < Np) B[(f * Np + n) * 16] = acc[f][mt][jj];
                     }
+            float *rtl = rt + 16 * w + lc, *otl = ot + 16 * w + lc;
+#pragma unroll
+            for (int rg = 0; rg < RGN; ++rg) {
+                const int row = 16 * rg + lr;
+                if (row < 3 * Np) {
+                    const floatx4 rh = *reinterpret_cast<const floatx4 *>(Bs + row * 16 + lc);
+                    floatx4 r, qo;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        r[q] = A.a * rr[rg][q] + A.dt * rh[q];
+                        qo[q] = qv[rg][q] + A.b * r[q];
+                    }
+                    *reinterpret_cast<floatx4 *>(rtl + (unsigned)(row * 64)) = r;
+                    *reinterpret_cast<floatx4 *>(otl + (unsigned)(row * 64)) = qo;
+                }
+            }
             if (tl + GB < xcount) load_res(xbase + tl + GB);
         }
         __syncthreads();
