@@ -102,6 +102,14 @@ __device__ __forceinline__ void pow2_scale(float mx, float &scale, float &unscal
 #ifndef DGW_SP_PSLEEP
 #define DGW_SP_PSLEEP 0
 #endif
+// Consumers load their FP64 factors and face data one tile ahead (1), and
+// their residual rows at tile start instead of one tile ahead (1).
+#ifndef DGW_SP_GPF
+#define DGW_SP_GPF 1
+#endif
+#ifndef DGW_SP_RSTART
+#define DGW_SP_RSTART 0
+#endif
 
 template <int N, bool MAT, int PREC>
 __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
@@ -216,7 +224,26 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                                    : floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
-    if (!producer) load_res(xbase + bi);
+    // FP64 geometric factors and face data of the lane's element (with
+    // DGW_SP_GPF loaded one tile ahead, at the end of the previous tile)
+    double gdn[G], fdn[3][FG];
+    auto load_geo = [&](int tile) {
+        int ln = lane0;
+        asm volatile("" : "+v"(ln));
+        const int col = 16 * w + (ln & 15);
+        const double *gt = A.geo64 + (size_t)tile * (G * 64);
+#pragma unroll
+        for (int q = 0; q < G; ++q) gdn[q] = gt[q * 64 + col];
+        const double *ft = A.fgeo64 + (size_t)tile * (3 * FG * 64);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int q = 0; q < FG; ++q) fdn[f][q] = ft[(f * FG + q) * 64 + col];
+    };
+    if (!producer) {
+        if (!DGW_SP_RSTART) load_res(xbase + bi);
+        if (DGW_SP_GPF) load_geo(xbase + bi);
+    }
 
     int it = 0;
     for (int tl = bi; tl < xcount; tl += GB, ++it) {
@@ -238,23 +265,25 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             float *rt = A.res + (size_t)tile * (3 * Np * 64);
             float *ot = A.qout + (size_t)tile * (3 * Np * 64);
 
+            if (DGW_SP_RSTART) load_res(tile);
             floatx4 rr[RGN];
 #pragma unroll
             for (int rg = 0; rg < RGN; ++rg) rr[rg] = rrn[rg];
             // FP64 geometric factors and face data of column col
-            const double *gt = A.geo64 + (size_t)tile * (G * 64);
-            const double rx = gt[0 * 64 + col], ry = gt[1 * 64 + col], sx = gt[2 * 64 + col], sy = gt[3 * 64 + col];
-            double ieps = 1.0, imu = 1.0;
-            if (MAT) {
-                ieps = gt[(4 % G) * 64 + col];
-                imu = gt[(5 % G) * 64 + col];
-            }
-            const double *ft = A.fgeo64 + (size_t)tile * (3 * FG * 64);
-            double fd[3][FG];
+            if (!DGW_SP_GPF) load_geo(tile);
+            double gd[G], fd[3][FG];
+#pragma unroll
+            for (int q = 0; q < G; ++q) gd[q] = gdn[q];
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
-                for (int q = 0; q < FG; ++q) fd[f][q] = ft[(f * FG + q) * 64 + col];
+                for (int q = 0; q < FG; ++q) fd[f][q] = fdn[f][q];
+            const double rx = gd[0], ry = gd[1], sx = gd[2], sy = gd[3];
+            double ieps = 1.0, imu = 1.0;
+            if (MAT) {
+                ieps = gd[4 % G];
+                imu = gd[5 % G];
+            }
 
             // upwind flux of this wave's 16 elements (FP64 coefficients), in place
 #pragma unroll
@@ -447,7 +476,10 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     *reinterpret_cast<floatx4 *>(otl + (unsigned)(row * 64)) = qo;
                 }
             }
-            if (tl + GB < xcount) load_res(xbase + tl + GB);
+            if (tl + GB < xcount) {
+                if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
+                if (DGW_SP_GPF) load_geo(xbase + tl + GB);
+            }
         }
         __syncthreads();
     }

@@ -191,6 +191,14 @@ __device__ __forceinline__ void face_flux(const R (&d)[6], R nx, R ny, R nz, R h
 #ifndef DGW_3D_RPF_SPLIT
 #define DGW_3D_RPF_SPLIT 0
 #endif
+// Surface-loop K step at which the other fields' residual runs are loaded
+// (negative: at the update).
+#ifndef DGW_3D_RAT
+#define DGW_3D_RAT -1
+#endif
+#ifndef DGW_3D_RAT_SPLIT
+#define DGW_3D_RAT_SPLIT -1
+#endif
 // Scheduling fences of the FP32 kernel: bit 0 after each volume field, bit 1
 // after each LIFT K step (they bound the registers the compiler keeps live).
 #ifndef DGW_3D_SB
@@ -555,6 +563,9 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
             const __amdgpu_buffer_rsrc_t rr = rsrc(A.res + (size_t)tile * (64 * RS), TB);
             const __amdgpu_buffer_rsrc_t ro = rsrc(A.qout + (size_t)tile * (64 * RS), TB);
             constexpr int RPF = SPLIT ? DGW_3D_RPF_SPLIT : DGW_3D_RPF;
+            // K step of the surface loop at which the remaining residual runs
+            // are loaded (negative: at the update)
+            constexpr int RAT = SPLIT ? DGW_3D_RAT_SPLIT : DGW_3D_RAT;
             float rv[6][KV];
             auto load_res = [&](int f) {
 #pragma unroll
@@ -590,6 +601,10 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                 // FP32 LIFT, K step ks: lane group g evaluates face node 4 ks + g
 #pragma unroll
                 for (int ks = 0; ks < KL; ++ks) {
+                    if (ks == RAT) {
+#pragma unroll
+                        for (int f = RPF; f < 6; ++f) load_res(f);
+                    }
                     const int j = 4 * ks + g;
                     float m[6], pv[6];
                     const bool wall = traces(ks, ks % SPD, m, pv);
@@ -632,6 +647,10 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
                 const uint2 *sL = reinterpret_cast<const uint2 *>(sAq + 2 * FV);
 #pragma unroll
                 for (int ks = 0; ks < KLS; ++ks) {
+                    if (ks == RAT) {
+#pragma unroll
+                        for (int f = RPF; f < 6; ++f) load_res(f);
+                    }
                     // hi and lo parts of the flux rows, two BF16 per word
                     unsigned bhw[6][2], blw[6][2];
 #pragma unroll
@@ -704,7 +723,8 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
             // fields' were issued before the surface loop), then per field
             // the arithmetic and the stores
 #pragma unroll
-            for (int f = RPF; f < 6; ++f) load_res(f);
+            for (int f = RPF; f < 6; ++f)
+                if (RAT < 0 || RAT >= (SPLIT ? KLS : KL)) load_res(f);
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
                 float qv[KV];
