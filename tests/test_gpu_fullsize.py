@@ -101,3 +101,28 @@ def test_3d_one_step_many_units(prec):
         s.advance_steps(1, dt)
         l2, emax = compare(s.get_fields(), q1, f"3D 82944 tets {prec} one step")
     assert l2 < STEP_TOL[prec][0] and emax < STEP_TOL[prec][1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+def test_material_order7_multi_tile_one_step(prec):
+    """Order 7 on a material mesh large enough that every work-group of the
+    default launch walks two tiles (128 x 128 grid, 32768 triangles, 512
+    tiles): the material forms of the fused-operand and split kernels,
+    including the row-major update through the LDS sub-tile, against one
+    oracle LSRK4 step of random data with eps/mu jumps."""
+    m = inputs.tri_grid(128, seed=11, permute=True)
+    m.eps = inputs.disk_inclusion_eps(m, (0.1, -0.2), 0.45)
+    m.mu = np.where(np.arange(m.K) % 3 == 0, 1.5, 1.0)
+    d = oracle.Discretization2D(m.vx, m.vy, m.elem_verts, 7, eps=m.eps, mu=m.mu)
+    op = oracle.Maxwell2D(d, 1.0)
+    dt = cfl_dt(d, 7)
+    q0 = np.random.default_rng(11).standard_normal((3, d.K, d.Np))
+    q1, res = q0.copy(), np.zeros_like(q0)
+    op.lsrk4_step(q1, res, dt)
+    with dgw.Solver(m, 7, prec=prec) as s:
+        if prec == "fp32":
+            assert s.info()["kernel"] == 2
+        s.set_fields(q0)
+        s.advance_steps(1, dt)
+        l2, emax = compare(s.get_fields(), q1, f"material N=7 32768 triangles {prec} one step")
+    assert l2 < STEP_TOL[prec][0] and emax < STEP_TOL[prec][1]
