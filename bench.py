@@ -243,13 +243,30 @@ def main():
     stream = torch.cuda.Stream()
     mode3 = (mode[0], mode[1], mode[2] if dim == 3 else 0)
 
-    def timed(prec):
+    def timed(prec, to_t1=False):
         """Warm up, then time exactly args.steps steps on the solver's stream
         with HIP events recorded on that stream; the fields start from the
-        device-initialised mode."""
+        device-initialised mode.  With to_t1 the solver first advances the
+        mode to t = 1 at the CFL step (the accuracy run, error against the
+        closed form returned) and the warm-up and timed steps follow it on
+        the same solver without an idle gap."""
         solver = dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec)
         dt = solver.cfl_dt()
         solver.set_cavity_mode(*mode)
+        t0, acc, q1 = 0.0, None, None
+        if to_t1:
+            # the fields at t = 1 are kept (one device copy) and their error
+            # evaluated after the timed steps: the FP64 closed-form reduction
+            # takes ~10 ms, a pause for the stage kernel
+            if prec != "fp64":
+                q1 = torch.empty(solver.shape, dtype=torch.float32, device="cuda")
+            n1 = solver.advance(1.0)
+            t0 = 1.0
+            if q1 is None:
+                acc = (solver.cavity_error(*mode3, 1.0), n1)
+            else:
+                solver.get_fields_dev(q1, stream)
+                acc = n1
         solver.tune = solver.autotune() if args.autotune else None
         solver.launch_steps(args.warmup, dt, stream)
         torch.cuda.synchronize()
@@ -260,18 +277,18 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
-        t_reached = (args.warmup + args.steps) * dt
+        t_reached = t0 + (args.warmup + args.steps) * dt
         err = solver.cavity_error(*mode3, t_reached)
         log(f"{prec}: {args.steps} steps in {ms:.2f} ms ({ms / (5 * args.steps) * 1e3:.1f} us per stage)")
+        if q1 is not None:
+            solver.set_fields_dev(q1, stream)
+            torch.cuda.synchronize()
+            acc = (solver.cavity_error(*mode3, 1.0), acc)
+            del q1
+        if acc is not None:
+            log(f"{prec}: t = 1 in {acc[1]} steps, rel L2 vs closed form {acc[0]:.3e}")
+        solver.acc_t1 = acc
         return solver, dt, ms, t_reached, err
-
-    def err_at_t1(prec):
-        with dgw.Solver(mesh, N, stream=stream, kernel=args.kernel, prec=prec) as s1:
-            s1.set_cavity_mode(*mode)
-            n = s1.advance(1.0)
-            e = s1.cavity_error(*mode3, 1.0)
-        log(f"{prec}: t = 1 in {n} steps, rel L2 vs closed form {e:.3e}")
-        return e, n
 
     log(f"{args.config}: K = {mesh.K}, N = {N}")
     if args.variants is None:
@@ -279,15 +296,13 @@ def main():
     else:
         vlist = [] if args.variants == "none" else [v for v in args.variants.split(",") if v]
     # Each precision's accuracy run to t = 1 (thousands of steps) comes right
-    # before its warm-up and timed steps, so that every precision is timed in
-    # the same sustained state of the GPU: after an idle gap the stage
-    # kernels' duration swings by up to a third over the first ~100 launches
-    # while the clocks settle, which a 20-step window would otherwise catch
-    # for the first precision only.
-    t1 = {}
-    if args.prec in vlist:
-        t1[args.prec] = err_at_t1(args.prec)
-    solver, dt, ms, t_reached, err = timed(args.prec)
+    # before its warm-up and timed steps, on the same solver, so that every
+    # precision is timed in the sustained state of the GPU: after an idle gap
+    # the stage kernels' duration swings by up to a third over the first ~100
+    # launches while the clocks settle, which a 20-step window right after a
+    # solver's set-up would catch.
+    solver, dt, ms, t_reached, err = timed(args.prec, to_t1=args.prec in vlist)
+    t1 = {args.prec: solver.acc_t1}
     bytes_per_launch, flops_per_launch = solver.stage_cost()
     dofs = solver.n_fields * solver.K * solver.Np
     value = dofs * args.steps / (ms * 1e-3)
@@ -342,8 +357,8 @@ def main():
                 v_ms = ms
                 e1, n1 = t1[prec]
             else:
-                e1, n1 = err_at_t1(prec)
-                sv, _, v_ms, _, _ = timed(prec)
+                sv, _, v_ms, _, _ = timed(prec, to_t1=True)
+                e1, n1 = sv.acc_t1
                 sv.close()
             var[prec] = {"value": dofs * args.steps / (v_ms * 1e-3), "ms_per_step": v_ms / args.steps,
                          "us_per_stage": v_ms * 1e3 / (5 * args.steps),
