@@ -110,6 +110,11 @@ __device__ __forceinline__ void pow2_scale(float mx, float &scale, float &unscal
 #ifndef DGW_SP_RSTART
 #define DGW_SP_RSTART 0
 #endif
+// Where in the tile the next tile's prefetches are issued: 0 after the
+// update, 1 before it, 2 at tile start.
+#ifndef DGW_SP_PFAT
+#define DGW_SP_PFAT 1
+#endif
 
 template <int N, bool MAT, int PREC>
 __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
@@ -224,6 +229,9 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                                    : floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
+    // the material forms and order 8 keep their prefetches at the end of
+    // the tile (registers)
+    constexpr int PFAT = (MAT || N > 7) ? 0 : DGW_SP_PFAT;
     // FP64 geometric factors and face data of the lane's element (with
     // DGW_SP_GPF loaded one tile ahead, at the end of the previous tile)
     double gdn[G], fdn[3][FG];
@@ -278,6 +286,10 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int q = 0; q < FG; ++q) fd[f][q] = fdn[f][q];
+            if (PFAT == 2 && tl + GB < xcount) {
+                if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
+                if (DGW_SP_GPF) load_geo(xbase + tl + GB);
+            }
             const double rx = gd[0], ry = gd[1], sx = gd[2], sy = gd[3];
             double ieps = 1.0, imu = 1.0;
             if (MAT) {
@@ -439,6 +451,10 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     for (int jj = 0; jj < 4; ++jj) acc[f][mt][jj] = cv[f][mt][jj] + t[mt][jj] * unscale;
             }
 
+            if (PFAT == 1 && tl + GB < xcount) {
+                if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
+                if (DGW_SP_GPF) load_geo(xbase + tl + GB);
+            }
             // fused low-storage RK update, row-major: the lane's q_in rows are
             // read first, the right-hand side (rows 16mt+4g+jj of column c) is
             // written over the sub-tile's field rows and read back row-major
@@ -476,7 +492,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     *reinterpret_cast<floatx4 *>(otl + (unsigned)(row * 64)) = qo;
                 }
             }
-            if (tl + GB < xcount) {
+            if (PFAT == 0 && tl + GB < xcount) {
                 if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
                 if (DGW_SP_GPF) load_geo(xbase + tl + GB);
             }
