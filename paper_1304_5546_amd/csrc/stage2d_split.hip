@@ -229,11 +229,13 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                                    : floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
-    // the material forms and order 8 keep their prefetches at the end of
-    // the tile (registers)
-    constexpr int PFAT = (MAT || N > 7) ? 0 : DGW_SP_PFAT;
+    // The factor prefetch and the early placement cost registers: below
+    // order 6 (where two work-groups share a CU) both are off, and the
+    // material forms and order 8 keep the prefetches at the end of the tile.
+    constexpr bool GPF = DGW_SP_GPF && N >= 6;
+    constexpr int PFAT = (MAT || N > 7 || N < 6) ? 0 : DGW_SP_PFAT;
     // FP64 geometric factors and face data of the lane's element (with
-    // DGW_SP_GPF loaded one tile ahead, at the end of the previous tile)
+    // GPF loaded one tile ahead, at the end of the previous tile)
     double gdn[G], fdn[3][FG];
     auto load_geo = [&](int tile) {
         int ln = lane0;
@@ -250,7 +252,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
     };
     if (!producer) {
         if (!DGW_SP_RSTART) load_res(xbase + bi);
-        if (DGW_SP_GPF) load_geo(xbase + bi);
+        if (GPF) load_geo(xbase + bi);
     }
 
     int it = 0;
@@ -278,7 +280,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
 #pragma unroll
             for (int rg = 0; rg < RGN; ++rg) rr[rg] = rrn[rg];
             // FP64 geometric factors and face data of column col
-            if (!DGW_SP_GPF) load_geo(tile);
+            if (!GPF) load_geo(tile);
             double gd[G], fd[3][FG];
 #pragma unroll
             for (int q = 0; q < G; ++q) gd[q] = gdn[q];
@@ -288,7 +290,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                 for (int q = 0; q < FG; ++q) fd[f][q] = fdn[f][q];
             if (PFAT == 2 && tl + GB < xcount) {
                 if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
-                if (DGW_SP_GPF) load_geo(xbase + tl + GB);
+                if (GPF) load_geo(xbase + tl + GB);
             }
             const double rx = gd[0], ry = gd[1], sx = gd[2], sy = gd[3];
             double ieps = 1.0, imu = 1.0;
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
 
             if (PFAT == 1 && tl + GB < xcount) {
                 if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
-                if (DGW_SP_GPF) load_geo(xbase + tl + GB);
+                if (GPF) load_geo(xbase + tl + GB);
             }
             // fused low-storage RK update, row-major: the lane's q_in rows are
             // read first, the right-hand side (rows 16mt+4g+jj of column c) is
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             }
             if (PFAT == 0 && tl + GB < xcount) {
                 if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
-                if (DGW_SP_GPF) load_geo(xbase + tl + GB);
+                if (GPF) load_geo(xbase + tl + GB);
             }
         }
         __syncthreads();
