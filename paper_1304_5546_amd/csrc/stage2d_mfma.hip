@@ -35,6 +35,21 @@ namespace dgw {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// 4x4x1 products for a last M-tile of at most 4 rows (1) or 16x16x4 (0).
+#ifndef DGW_MF_TAIL4
+#define DGW_MF_TAIL4 1
+#endif
+// Orders whose last 16-row M-tile holds at most 4 operator rows (with two or
+// more M-tiles): those rows are contracted on v_mfma_f32_4x4x1f32 (16 blocks
+// of 4x4, a quarter of the 16x16x4 product's matrix-core time).  Block b =
+// lane/4 takes K row 4 ks + b/4 and columns 4 (b%4) .. + 3, so the B
+// fragment is the 16x16x4 one unchanged; A holds rows 16 (MT-1) + lane%4;
+// the four K-partitions are summed across lane groups after the K loops.
+constexpr bool tail4_rows(int N) {
+    const int Np = (N + 1) * (N + 2) / 2, MT = (Np + 15) / 16;
+    return DGW_MF_TAIL4 && MT >= 2 && Np - 16 * (MT - 1) <= 4;
+}
+
 namespace {
 
 template <int N, bool MAT>
@@ -45,6 +60,8 @@ struct Tri {
     static constexpr int Kd = 2 * Np + Nafp;
     static constexpr int KS = (Kd + 3) / 4;
     static constexpr int MT = (Np + 15) / 16;
+    // the last M-tile holds at most 4 rows: contracted on 4x4x1 products
+    static constexpr bool TAIL4 = tail4_rows(N);
     static constexpr int KV = (2 * Np) / 4;  // K-steps made only of volume columns
     static constexpr int G = MAT ? 6 : 4;    // per-element factor rows
     static constexpr int FG = MAT ? 6 : 3;   // per-face data rows
@@ -298,9 +315,15 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const float a = sa[(mt * KS + ks) * 64 + lane];
-                    acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][mt], 0, 0, 0);
-                    acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][mt], 0, 0, 0);
-                    acc[2][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, acc[2][mt], 0, 0, 0);
+                    if (T::TAIL4 && mt == MT - 1) {
+                        acc[0][mt] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b0, acc[0][mt], 0, 0, 0);
+                        acc[1][mt] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b1, acc[1][mt], 0, 0, 0);
+                        acc[2][mt] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b2, acc[2][mt], 0, 0, 0);
+                    } else {
+                        acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][mt], 0, 0, 0);
+                        acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][mt], 0, 0, 0);
+                        acc[2][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, acc[2][mt], 0, 0, 0);
+                    }
                 }
                 // keep the operand reads of later K-steps from being hoisted
                 // into long-lived registers
@@ -368,15 +391,35 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const float a = sa[(mt * KS + ks) * 64 + lane];
-                    acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][mt], 0, 0, 0);
-                    acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][mt], 0, 0, 0);
-                    acc[2][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, acc[2][mt], 0, 0, 0);
+                    if (T::TAIL4 && mt == MT - 1) {
+                        acc[0][mt] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b0, acc[0][mt], 0, 0, 0);
+                        acc[1][mt] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b1, acc[1][mt], 0, 0, 0);
+                        acc[2][mt] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b2, acc[2][mt], 0, 0, 0);
+                    } else {
+                        acc[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][mt], 0, 0, 0);
+                        acc[1][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][mt], 0, 0, 0);
+                        acc[2][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, acc[2][mt], 0, 0, 0);
+                    }
                 }
                 // keep the operand reads of later K-steps from being hoisted
                 // into long-lived registers
                 if (DGW_MF_SB > 0 && ks % DGW_MF_SB == DGW_MF_SB - 1) __builtin_amdgcn_sched_barrier(0);
             }
 
+            // 4x4x1 tail: sum the four K-partitions (lane groups) of rows
+            // 16 (MT-1) + jj; lane group 0 then holds them as the 16x16x4
+            // layout would
+            if constexpr (T::TAIL4) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        float v = acc[f][MT - 1][jj];
+                        v += __shfl_xor(v, 16);
+                        v += __shfl_xor(v, 32);
+                        acc[f][MT - 1][jj] = v;
+                    }
+            }
             // fused low-storage RK update, row-major.  The lane's q_in rows are
             // read first; the right-hand side (rows 16mt+4g+jj of column c in
             // the accumulators) is then written over the sub-tile's field rows
@@ -491,7 +534,8 @@ int opsfrag2d(int N, const double *Dr, const double *Ds, const double *LIFT, flo
     for (int mt = 0; mt < MT; ++mt)
         for (int ks = 0; ks < KS; ++ks)
             for (int l = 0; l < 64; ++l) {
-                const int row = 16 * mt + (l % 16), k = 4 * ks + l / 16;
+                // the 4x4x1 tail takes rows 16 mt + l%4 (see tail4_rows)
+                const int row = 16 * mt + ((tail4_rows(N) && mt == MT - 1) ? l % 4 : l % 16), k = 4 * ks + l / 16;
                 double v = 0.0;
                 if (row < Np && k < Kd) {
                     if (k < Np)
