@@ -261,17 +261,28 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
     };
     if (XRES && !producer) load_res(xbase + bi);
 
-    int it = 0;
-    for (int tl = bi; tl < xcount; tl += GB, ++it) {
-        const int cur = it & 1;
-        if (producer) {
+    // Producer and consumer waves run separate tile loops with the same
+    // (wave-uniform) trip count and one barrier per tile each: the barrier
+    // counts waves, not program locations.  One loop with a role branch
+    // inside would join the roles' register state at the barrier, and the
+    // compiler would copy the consumers' in-flight prefetch registers there
+    // (waiting for the loads).
+    if (producer) {
+        int it = 0;
+        for (int tl = bi; tl < xcount; tl += GB, ++it) {
+            const int cur = it & 1;
             const int tn = tl + GB;
             if (DGW_MF_PSLEEP > 0) __builtin_amdgcn_s_sleep(DGW_MF_PSLEEP);
             if (tn < xcount) {
                 produce(xbase + tn, cur ^ 1);
                 if (tn + GB < xcount) load_recs(xbase + tn + GB);
             }
-        } else {
+            __syncthreads();
+        }
+    } else {
+        int it = 0;
+        for (int tl = bi; tl < xcount; tl += GB, ++it) {
+            const int cur = it & 1;
             const int tile = xbase + tl;
             const TileSrc S = tile_src<BATCH>(A, tile);
             float *rt = S.res + (size_t)S.tile * (3 * Np * 64);
@@ -458,9 +469,12 @@ __global__ void __launch_bounds__(512) stage2d_mfma_kernel(StageArgs A) {
                     *reinterpret_cast<floatx4 *>(otl + (unsigned)(row * 64)) = qo;
                 }
             }
-            if (XRES && tl + GB < xcount) load_res(xbase + tl + GB);
+            // unconditional (the last tile re-reads its own rows, unused): a
+            // conditional prefetch makes the compiler copy the loop-carried
+            // registers, waiting for the loads, before the barrier
+            if (XRES) load_res(xbase + (tl + GB < xcount ? tl + GB : tl));
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 

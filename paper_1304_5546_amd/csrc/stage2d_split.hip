@@ -255,17 +255,28 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
         if (GPF) load_geo(xbase + bi);
     }
 
-    int it = 0;
-    for (int tl = bi; tl < xcount; tl += GB, ++it) {
-        const int cur = it & 1;
-        if (producer) {
+    // Producer and consumer waves run separate tile loops with the same
+    // (wave-uniform) trip count and one barrier per tile each (the barrier
+    // counts waves, not program locations): with one loop and a role branch
+    // inside, the roles' register state would join at the barrier and the
+    // compiler would copy the consumers' in-flight prefetch registers there,
+    // waiting for the loads.
+    if (producer) {
+        int it = 0;
+        for (int tl = bi; tl < xcount; tl += GB, ++it) {
+            const int cur = it & 1;
             const int tn = tl + GB;
             if (DGW_SP_PSLEEP > 0) __builtin_amdgcn_s_sleep(DGW_SP_PSLEEP);
             if (tn < xcount) {
                 produce(xbase + tn, cur ^ 1);
                 if (tn + GB < xcount) load_recs(xbase + tn + GB);
             }
-        } else {
+            __syncthreads();
+        }
+    } else {
+        int it = 0;
+        for (int tl = bi; tl < xcount; tl += GB, ++it) {
+            const int cur = it & 1;
             const int tile = xbase + tl;
             int lane = lane0;
             asm volatile("" : "+v"(lane));
@@ -288,9 +299,13 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int q = 0; q < FG; ++q) fd[f][q] = fdn[f][q];
-            if (PFAT == 2 && tl + GB < xcount) {
-                if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
-                if (GPF) load_geo(xbase + tl + GB);
+            if (PFAT == 2) {
+                // unconditional (the last tile re-reads its own data, unused):
+                // a conditional prefetch makes the compiler copy the
+                // loop-carried registers, waiting for the loads
+                const int tp = xbase + (tl + GB < xcount ? tl + GB : tl);
+                if (!DGW_SP_RSTART) load_res(tp);
+                if (GPF) load_geo(tp);
             }
             const double rx = gd[0], ry = gd[1], sx = gd[2], sy = gd[3];
             double ieps = 1.0, imu = 1.0;
@@ -453,9 +468,13 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     for (int jj = 0; jj < 4; ++jj) acc[f][mt][jj] = cv[f][mt][jj] + t[mt][jj] * unscale;
             }
 
-            if (PFAT == 1 && tl + GB < xcount) {
-                if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
-                if (GPF) load_geo(xbase + tl + GB);
+            if (PFAT == 1) {
+                // unconditional (the last tile re-reads its own data, unused):
+                // a conditional prefetch makes the compiler copy the
+                // loop-carried registers, waiting for the loads
+                const int tp = xbase + (tl + GB < xcount ? tl + GB : tl);
+                if (!DGW_SP_RSTART) load_res(tp);
+                if (GPF) load_geo(tp);
             }
             // fused low-storage RK update, row-major: the lane's q_in rows are
             // read first, the right-hand side (rows 16mt+4g+jj of column c) is
@@ -494,12 +513,16 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     *reinterpret_cast<floatx4 *>(otl + (unsigned)(row * 64)) = qo;
                 }
             }
-            if (PFAT == 0 && tl + GB < xcount) {
-                if (!DGW_SP_RSTART) load_res(xbase + tl + GB);
-                if (GPF) load_geo(xbase + tl + GB);
+            if (PFAT == 0) {
+                // unconditional (the last tile re-reads its own data, unused):
+                // a conditional prefetch makes the compiler copy the
+                // loop-carried registers, waiting for the loads
+                const int tp = xbase + (tl + GB < xcount ? tl + GB : tl);
+                if (!DGW_SP_RSTART) load_res(tp);
+                if (GPF) load_geo(tp);
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
