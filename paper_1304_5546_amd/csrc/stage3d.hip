@@ -255,6 +255,15 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
     // operands, loaded during this unit's surface phase
     float nG[9], nb0[Tet<N>::KV];
     bool npf_ok = false;
+    // gathered partner traces of the face-node slots in flight: zeroed once
+    // here, not per unit (a per-unit zero of the in-window lanes after the
+    // masked loads of the others would make the compiler wait for those
+    // loads right away, before the barrier they are meant to cross)
+    float rval[SPLIT ? DGW_3D_SPD_SPLIT : DGW_3D_SPD][6];
+#pragma unroll
+    for (int t = 0; t < (SPLIT ? DGW_3D_SPD_SPLIT : DGW_3D_SPD); ++t)
+#pragma unroll
+        for (int f = 0; f < 6; ++f) rval[t][f] = 0.f;
     for (int pl = bi; pl < xcount; pl += GB) {
         const int pair = xbase + pl;
         const int tile = 2 * pair + (w >> 2);
@@ -511,7 +520,6 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
         // node and the wall flag (rown), the partner's LDS offset when it lies
         // in the pair (rloc >= 0), else its six values gathered from memory
         // (rval)
-        float rval[SPD][6];
         int rown[SPD], rloc[SPD];
         const float *sFf = &sF[0][0];
         auto gather = [&](int t, int slot) {
@@ -546,8 +554,6 @@ __global__ void __launch_bounds__(512) stage3d_kernel(StageArgs A) {
         for (int t = 0; t < SPD; ++t) {
             rown[t] = 0;
             rloc[t] = 0;
-#pragma unroll
-            for (int f = 0; f < 6; ++f) rval[t][f] = 0.f;
         }
         if (active) {
 #pragma unroll
