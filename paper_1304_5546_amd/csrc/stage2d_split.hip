@@ -368,15 +368,24 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             for (int sf = 0; sf < 3; ++sf) {  // Hx, Hy, Ez
                 const float uc = B[(sf * Np + CN) * 16];
                 // FP16 (5-bit exponent): scale the operand column by a power of
-                // two so that its largest entry is below 2^14, undo it exactly
+                // two so that its largest entry is below 2^14, undo it exactly;
+                // the column maximum is taken over the lane's own operand
+                // entries (K row 32 ks + 8 g + q), read once for both uses
+                float vr[KV][8];
                 float scale = 1.f, unscale = 1.f;
                 if constexpr (PREC == 2) {
+#pragma unroll
+                    for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int k = 32 * ks + 8 * g + q;
+                            vr[ks][q] = k < Np ? B[(sf * Np + k) * 16] - uc : 0.f;
+                        }
                     float mx = 0.f;
 #pragma unroll
-                    for (int nb = 0; nb < (Np + 3) / 4; ++nb) {
-                        const int n = 4 * nb + g;
-                        if (n < Np) mx = fmaxf(mx, fabsf(B[(sf * Np + n) * 16] - uc));
-                    }
+                    for (int ks = 0; ks < KV; ++ks)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fabsf(vr[ks][q]));
                     pow2_scale(mx, scale, unscale);
                 }
                 floatx4 d[2][MT];
@@ -391,8 +400,13 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     hv bh, bl;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const int k = 32 * ks + 8 * g + q;
-                        const float v = k < Np ? (B[(sf * Np + k) * 16] - uc) * scale : 0.f;
+                        float v;
+                        if constexpr (PREC == 2) {
+                            v = vr[ks][q] * scale;
+                        } else {
+                            const int k = 32 * ks + 8 * g + q;
+                            v = k < Np ? B[(sf * Np + k) * 16] - uc : 0.f;
+                        }
                         const h16 hi = (h16)v;
                         bh[q] = hi;
                         bl[q] = (h16)(v - (float)hi);
@@ -432,14 +446,21 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
             floatx4 acc[3][MT];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
+                float vr[KF][8];
                 float scale = 1.f, unscale = 1.f;
                 if constexpr (PREC == 2) {
+#pragma unroll
+                    for (int ks = 0; ks < KF; ++ks)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int k = 32 * ks + 8 * g + q;
+                            vr[ks][q] = k < Nafp ? B[(RP + f * Nafp + k) * 16] : 0.f;
+                        }
                     float mx = 0.f;
 #pragma unroll
-                    for (int jb = 0; jb < (Nafp + 3) / 4; ++jb) {
-                        const int jn = 4 * jb + g;
-                        if (jn < Nafp) mx = fmaxf(mx, fabsf(B[(RP + f * Nafp + jn) * 16]));
-                    }
+                    for (int ks = 0; ks < KF; ++ks)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fabsf(vr[ks][q]));
                     pow2_scale(mx, scale, unscale);
                 }
                 floatx4 t[MT];
@@ -450,8 +471,13 @@ __global__ void __launch_bounds__(512) stage2d_split_kernel(StageArgs A) {
                     hv bh, bl;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const int k = 32 * ks + 8 * g + q;
-                        const float v = k < Nafp ? B[(RP + f * Nafp + k) * 16] * scale : 0.f;
+                        float v;
+                        if constexpr (PREC == 2) {
+                            v = vr[ks][q] * scale;
+                        } else {
+                            const int k = 32 * ks + 8 * g + q;
+                            v = k < Nafp ? B[(RP + f * Nafp + k) * 16] : 0.f;
+                        }
                         const h16 hi = (h16)v;
                         bh[q] = hi;
                         bl[q] = (h16)(v - (float)hi);
