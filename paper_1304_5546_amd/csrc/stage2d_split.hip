@@ -81,11 +81,23 @@ __device__ __forceinline__ floatx4 mfma3(uint4 ahu, uint4 alu, typename P16<PREC
     return P16<PREC>::mfma(al, bh, c);
 }
 
+// Maximum of x over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the four lane
+// groups of a column).  A row swap of x with itself hands each row of 16
+// lanes its partner row's values (16-lane rows paired within each half,
+// then the two halves), on the VALU rather than through the LDS crossbar.
+__device__ __forceinline__ float col_max(float x) {
+    const unsigned u = __float_as_uint(x);
+    const auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    x = fmaxf(__uint_as_float(r16[0]), __uint_as_float(r16[1]));
+    const unsigned v = __float_as_uint(x);
+    const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return fmaxf(__uint_as_float(r32[0]), __uint_as_float(r32[1]));
+}
+
 // Power-of-two scale taking a column maximum mx (per lane group) below 2^14,
 // reduced over the four lane groups of the column.
 __device__ __forceinline__ void pow2_scale(float mx, float &scale, float &unscale) {
-    mx = fmaxf(mx, __shfl_xor(mx, 16));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    mx = col_max(mx);
     scale = unscale = 1.f;
     if (mx > 0.f && mx < 3.0e38f) {
         int ex;
